@@ -1,0 +1,139 @@
+/*
+ * libpa: the G_{c,d} privacy-amplification hash on an MI355X (gfx950) GPU.
+ *
+ * The hash is the modular-arithmetic universal_2 family of Section 2.3,
+ * eq. (6) and the g_{c,d} definition after it:
+ *
+ *     G_{c,d} = { g_{c,d} : c, d in Z_{2^n}, c odd },
+ *     g_{c,d}(x) = floor( ((c x + d) mod 2^n) / 2^(n - m) ),
+ *
+ * evaluated in the order of the scheme of Section 3.2: multiply-add (3.2.2),
+ * reduction mod 2^n (3.2.3), export (3.2.4) and selection of the most
+ * significant r = m bits (3.2.5).  x is the n-bit corrected key, the output is
+ * the m-bit final key.  The large multiply is an exact NTT convolution (the
+ * approach of Alg. 1) over three 31-bit primes, done by HIP kernels.
+ *
+ * Bit layout (all arrays): little-endian 64-bit words, word 0 least
+ * significant; bit i of a value is bit (i % 64) of word i / 64.  Inputs have
+ * ceil(n/64) words and bits >= n of their top word are ignored.  Outputs have
+ * ceil(m/64) words and bits >= m of the top word are written as 0.  Output bit
+ * j is bit (n - m + j) of V = (c x + d) mod 2^n; leading zeros of V count.
+ *
+ * Seeds (the paper chooses g at random and publicly, Section 2.2): word i of
+ * the stream of seed s is the i-th output of SplitMix64(s) (Steele, Lea and
+ * Flood, OOPSLA 2014).  c is the stream of seed_a masked to n bits with bit 0
+ * set; d is the stream of seed_b masked to n bits.  This generator is not
+ * cryptographic: a deployment passes true random c and d through pa_hash_ex.
+ *
+ * Errors: every call returns PA_OK or a PA_E* code; no exception crosses the
+ * ABI.  On error the output is unspecified and the context stays usable;
+ * pa_last_error() gives a text for the last failure on that context.
+ *
+ * Ownership and threads: the caller owns every key, operand and output buffer.
+ * A context owns its device workspace, tables and stream and frees them in
+ * pa_destroy().  A context is not thread-safe; several contexts may coexist.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pa_status {
+    PA_OK = 0,
+    PA_EINVAL = 1,   /* null pointer, n == 0, m == 0, m > n, n > PA_MAX_N, even c */
+    PA_ENOMEM = 2,   /* host or device allocation failed */
+    PA_EDEVICE = 3,  /* a HIP runtime call failed (see pa_last_error) */
+    PA_ENODEV = 4,   /* no usable gfx950 device with that index */
+};
+
+/* Largest block: 2^24 32-bit digits (transform length 2^25, the smallest
+ * 2-adicity of the three primes). */
+#define PA_MAX_N ((uint64_t)1 << 29)
+
+typedef struct pa_ctx pa_ctx;
+
+/* Create a context on HIP device `device` (its own stream and tables). */
+int pa_init(pa_ctx **ctx, int device);
+
+/* Release the context and everything it owns.  NULL is allowed. */
+void pa_destroy(pa_ctx *ctx);
+
+/* Static text for a status code. */
+const char *pa_strerror(int status);
+
+/* Text describing the last failure on ctx (empty if none). */
+const char *pa_last_error(const pa_ctx *ctx);
+
+/*
+ * Synchronous, host memory in and out.
+ *   key:  ceil(n/64) words (host), the n-bit corrected key x
+ *   out:  ceil(m/64) words (host), written with the m-bit final key
+ * c and d are expanded from seed_a and seed_b on the device.
+ */
+int pa_hash(pa_ctx *ctx, const uint64_t *key, uint64_t seed_a, uint64_t seed_b,
+            uint64_t n, uint64_t m, uint64_t *out);
+
+/*
+ * Synchronous with explicit operands (host memory): c and d are ceil(n/64)
+ * words each.  c must be odd (eq. (6)); an even c returns PA_EINVAL.
+ */
+int pa_hash_ex(pa_ctx *ctx, const uint64_t *key, const uint64_t *c, const uint64_t *d,
+               uint64_t n, uint64_t m, uint64_t *out);
+
+/*
+ * Asynchronous, device memory: d_key (ceil(n/64) words) and d_out (ceil(m/64)
+ * words) are device pointers; the work is queued on `stream` (a hipStream_t,
+ * NULL for the null stream) and the call returns without waiting.  The
+ * context's workspace is reused by every call, so calls on one context must
+ * be ordered (one stream, or the caller synchronises between streams).  The
+ * workspace grows, with a device synchronisation, when n exceeds every
+ * earlier call; pa_reserve() avoids that inside a timed or captured region.
+ */
+int pa_hash_async(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_t seed_b,
+                  uint64_t n, uint64_t m, uint64_t *d_out, void *stream);
+
+/*
+ * Per-launch timing of one pa_hash_async call, for measurement.  The same
+ * kernels run as in pa_hash_async; a HIP event is recorded on `stream` around
+ * every launch and the call waits for the stream before returning.
+ *   kind:  PA_K_* of each launch
+ *   ms:    its duration from the events
+ *   bytes: the bytes the launch must move at minimum (its algorithmic traffic)
+ */
+#define PA_PROFILE_MAX 32
+enum pa_kernel_kind {
+    PA_K_NTT_PASS = 0,    /* one LDS pass of a forward, fused or inverse NTT */
+    PA_K_CARRY_CHUNK = 1, /* CRT + column sums + per-chunk carry function */
+    PA_K_CARRY_SCAN = 2,  /* carry into every chunk */
+    PA_K_CARRY_APPLY = 3, /* CRT + carry resolve + digits of V */
+    PA_K_EXTRACT = 4,     /* bits [n-m, n) of V into output words */
+};
+typedef struct pa_profile {
+    int count;
+    int kind[PA_PROFILE_MAX];
+    float ms[PA_PROFILE_MAX];
+    uint64_t bytes[PA_PROFILE_MAX];
+} pa_profile;
+
+int pa_hash_profile(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_t seed_b,
+                    uint64_t n, uint64_t m, uint64_t *d_out, void *stream, pa_profile *prof);
+
+/* Size the workspace for blocks of up to n_max bits now. */
+int pa_reserve(pa_ctx *ctx, uint64_t n_max);
+
+/* Device bytes the workspace needs for one block of n bits. */
+uint64_t pa_workspace_bytes(uint64_t n);
+
+/* Transform length used for a block of n bits (a power of two). */
+uint64_t pa_transform_length(uint64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H */

@@ -1,0 +1,223 @@
+"""Python binding of libpa, the G_{c,d} privacy-amplification hash on MI355X.
+
+Thin ctypes marshalling over the C ABI declared in include/pa.h; every step of
+the hash runs in the library's HIP kernels.  The functions keep the C names:
+
+    ctx = pa_init(device=0)
+    y = pa_hash(ctx, key_words, seed_a, seed_b, n, m)          # host in/out
+    y = pa_hash_ex(ctx, key_words, c_words, d_words, n, m)     # explicit c, d
+    pa_hash_async(ctx, d_key, seed_a, seed_b, n, m, d_out)     # torch device tensors
+    prof = pa_hash_profile(ctx, d_key, seed_a, seed_b, n, m, d_out)
+    pa_destroy(ctx)
+
+Host arrays are numpy uint64 (little-endian words, bit i of the value at bit
+i % 64 of word i // 64).  Device buffers are torch tensors of 8-byte elements on
+a ROCm device; torch only provides their memory and the HIP stream.
+
+The library is built in-tree (``python -m paper_1910_04429_amd.build`` or
+``__graft_entry__.build()``).  If libpa.so is missing this module raises at
+import: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpa.so")
+
+PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENODEV = 0, 1, 2, 3, 4
+PA_MAX_N = 1 << 29
+PA_PROFILE_MAX = 32
+KERNEL_KINDS = {0: "ntt_pass", 1: "carry_chunk", 2: "carry_scan", 3: "carry_apply",
+                4: "extract"}
+
+
+class PAError(RuntimeError):
+    def __init__(self, status: int, text: str):
+        super().__init__(f"libpa status {status}: {text}")
+        self.status = status
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int),
+                ("kind", ctypes.c_int * PA_PROFILE_MAX),
+                ("ms", ctypes.c_float * PA_PROFILE_MAX),
+                ("bytes", ctypes.c_uint64 * PA_PROFILE_MAX)]
+
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u64 = ctypes.c_uint64
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_lib.pa_init.restype = ctypes.c_int
+_lib.pa_init.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+_lib.pa_destroy.restype = None
+_lib.pa_destroy.argtypes = [ctypes.c_void_p]
+_lib.pa_strerror.restype = ctypes.c_char_p
+_lib.pa_strerror.argtypes = [ctypes.c_int]
+_lib.pa_last_error.restype = ctypes.c_char_p
+_lib.pa_last_error.argtypes = [ctypes.c_void_p]
+_lib.pa_hash.restype = ctypes.c_int
+_lib.pa_hash.argtypes = [ctypes.c_void_p, _u64p, _u64, _u64, _u64, _u64, _u64p]
+_lib.pa_hash_ex.restype = ctypes.c_int
+_lib.pa_hash_ex.argtypes = [ctypes.c_void_p, _u64p, _u64p, _u64p, _u64, _u64, _u64p]
+_lib.pa_hash_async.restype = ctypes.c_int
+_lib.pa_hash_async.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _u64, _u64, _u64, _u64,
+                               ctypes.c_void_p, ctypes.c_void_p]
+_lib.pa_hash_profile.restype = ctypes.c_int
+_lib.pa_hash_profile.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _u64, _u64, _u64, _u64,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Profile)]
+_lib.pa_reserve.restype = ctypes.c_int
+_lib.pa_reserve.argtypes = [ctypes.c_void_p, _u64]
+_lib.pa_workspace_bytes.restype = _u64
+_lib.pa_workspace_bytes.argtypes = [_u64]
+_lib.pa_transform_length.restype = _u64
+_lib.pa_transform_length.argtypes = [_u64]
+
+MASK64 = (1 << 64) - 1
+
+
+def words(bits: int) -> int:
+    return (int(bits) + 63) // 64
+
+
+def _check(ctx, rc: int):
+    if rc != PA_OK:
+        detail = _lib.pa_last_error(ctx).decode() if ctx else ""
+        raise PAError(rc, f"{_lib.pa_strerror(rc).decode()} {detail}".strip())
+
+
+def _host_words(a, nwords: int, name: str) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+    if a.ndim != 1 or a.size < nwords:
+        raise ValueError(f"{name}: need {nwords} uint64 words, got shape {a.shape}")
+    return a
+
+
+def _dev_ptr(t, nwords: int, name: str) -> int:
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous() or t.element_size() != 8 or t.numel() < nwords:
+        raise ValueError(f"{name}: need a contiguous 8-byte tensor of >= {nwords} elements")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def pa_init(device: int = 0):
+    ctx = ctypes.c_void_p()
+    _check(None, _lib.pa_init(ctypes.byref(ctx), int(device)))
+    return ctx
+
+
+def pa_destroy(ctx) -> None:
+    if ctx:
+        _lib.pa_destroy(ctx)
+
+
+def pa_strerror(status: int) -> str:
+    return _lib.pa_strerror(status).decode()
+
+
+def pa_last_error(ctx) -> str:
+    return _lib.pa_last_error(ctx).decode()
+
+
+def pa_hash(ctx, key, seed_a: int, seed_b: int, n: int, m: int) -> np.ndarray:
+    key = _host_words(key, words(n), "key")
+    out = np.zeros(max(words(m), 1), dtype=np.uint64)
+    _check(ctx, _lib.pa_hash(ctx, key.ctypes.data_as(_u64p), seed_a & MASK64,
+                             seed_b & MASK64, n, m, out.ctypes.data_as(_u64p)))
+    return out
+
+
+def pa_hash_ex(ctx, key, c, d, n: int, m: int) -> np.ndarray:
+    w = words(n)
+    key, c, d = _host_words(key, w, "key"), _host_words(c, w, "c"), _host_words(d, w, "d")
+    out = np.zeros(max(words(m), 1), dtype=np.uint64)
+    _check(ctx, _lib.pa_hash_ex(ctx, key.ctypes.data_as(_u64p), c.ctypes.data_as(_u64p),
+                                d.ctypes.data_as(_u64p), n, m, out.ctypes.data_as(_u64p)))
+    return out
+
+
+def pa_hash_async(ctx, d_key, seed_a: int, seed_b: int, n: int, m: int, d_out,
+                  stream=None) -> None:
+    """Queue the hash of device tensor d_key into device tensor d_out."""
+    _check(ctx, _lib.pa_hash_async(ctx, _dev_ptr(d_key, words(n), "d_key"), seed_a & MASK64,
+                                   seed_b & MASK64, n, m, _dev_ptr(d_out, words(m), "d_out"),
+                                   _stream_handle(stream)))
+
+
+def pa_hash_profile(ctx, d_key, seed_a: int, seed_b: int, n: int, m: int, d_out,
+                    stream=None) -> list[dict]:
+    """Run once with a HIP event pair around every launch; returns one dict per launch."""
+    prof = _Profile()
+    _check(ctx, _lib.pa_hash_profile(ctx, _dev_ptr(d_key, words(n), "d_key"),
+                                     seed_a & MASK64, seed_b & MASK64, n, m,
+                                     _dev_ptr(d_out, words(m), "d_out"),
+                                     _stream_handle(stream), ctypes.byref(prof)))
+    return [{"kind": KERNEL_KINDS.get(prof.kind[i], str(prof.kind[i])),
+             "ms": float(prof.ms[i]), "bytes": int(prof.bytes[i])}
+            for i in range(prof.count)]
+
+
+def pa_reserve(ctx, n_max: int) -> None:
+    _check(ctx, _lib.pa_reserve(ctx, n_max))
+
+
+def pa_workspace_bytes(n: int) -> int:
+    return int(_lib.pa_workspace_bytes(n))
+
+
+def pa_transform_length(n: int) -> int:
+    return int(_lib.pa_transform_length(n))
+
+
+class Context:
+    """Owns one pa_ctx; a convenience wrapper over the functions above."""
+
+    def __init__(self, device: int = 0):
+        self.ctx = pa_init(device)
+
+    def close(self):
+        if self.ctx:
+            pa_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hash(self, key, seed_a, seed_b, n, m):
+        return pa_hash(self.ctx, key, seed_a, seed_b, n, m)
+
+    def hash_ex(self, key, c, d, n, m):
+        return pa_hash_ex(self.ctx, key, c, d, n, m)
+
+    def hash_async(self, d_key, seed_a, seed_b, n, m, d_out, stream=None):
+        pa_hash_async(self.ctx, d_key, seed_a, seed_b, n, m, d_out, stream)
+
+    def profile(self, d_key, seed_a, seed_b, n, m, d_out, stream=None):
+        return pa_hash_profile(self.ctx, d_key, seed_a, seed_b, n, m, d_out, stream)
+
+    def reserve(self, n_max):
+        pa_reserve(self.ctx, n_max)

@@ -1,0 +1,106 @@
+// Prime-field arithmetic for the exact number-theoretic-transform multiply.
+//
+// The hash needs the low n bits of c*x (Section 2.3, the g_{c,d} definition;
+// Section 3.2.2, the large multiply done by an NTT convolution as in Alg. 1).
+// Operands are cut into 32-bit digits; the convolution coefficients
+// sum_{i+j=k} x_i c_j are below D (2^32-1)^2 < 2^88 for D <= 2^24 digits and are
+// recovered exactly by CRT from three NTTs over 31-bit primes whose product is
+// about 2^92.6.  The primes are of the form k 2^t + 1 with t >= 25, so every
+// power-of-two length up to 2^25 has a root of unity in each field.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pa {
+
+constexpr int kNumPrimes = 3;
+constexpr int kLogMaxLen = 25;                 // min 2-adicity of the primes
+constexpr uint32_t kPrimes[kNumPrimes] = {
+    2013265921u,  // 15 * 2^27 + 1
+    1811939329u,  // 27 * 2^26 + 1
+    2113929217u,  // 63 * 2^25 + 1
+};
+
+// -p^{-1} mod 2^32 by Newton iteration (each step doubles the correct bits).
+constexpr uint32_t neg_inverse_u32(uint32_t p)
+{
+    uint32_t inv = p;  // correct to 3 bits for odd p
+    for (int i = 0; i < 5; ++i)
+        inv *= 2u - p * inv;
+    return 0u - inv;
+}
+
+constexpr uint32_t kNegInv[kNumPrimes] = {
+    neg_inverse_u32(kPrimes[0]), neg_inverse_u32(kPrimes[1]), neg_inverse_u32(kPrimes[2])};
+
+constexpr uint64_t pow_mod(uint64_t b, uint64_t e, uint64_t p)
+{
+    uint64_t r = 1 % p;
+    b %= p;
+    while (e) {
+        if (e & 1) r = r * b % p;
+        b = b * b % p;
+        e >>= 1;
+    }
+    return r;
+}
+
+constexpr uint32_t inv_mod(uint64_t a, uint64_t p) { return (uint32_t)pow_mod(a, p - 2, p); }
+
+// Montgomery form x 2^32 mod p of a constant.
+constexpr uint32_t to_mont(uint64_t x, uint64_t p) { return (uint32_t)(((x % p) << 32) % p); }
+
+// Garner CRT constants for (p0, p1, p2).
+constexpr uint64_t kP01 = (uint64_t)kPrimes[0] * kPrimes[1];
+constexpr uint32_t kInvP0ModP1M = to_mont(inv_mod(kPrimes[0] % kPrimes[1], kPrimes[1]), kPrimes[1]);
+constexpr uint32_t kP0ModP2M = to_mont(kPrimes[0] % kPrimes[2], kPrimes[2]);
+constexpr uint32_t kInvP01ModP2M = to_mont(inv_mod(kP01 % kPrimes[2], kPrimes[2]), kPrimes[2]);
+
+static_assert(kPrimes[0] > kPrimes[1] && kPrimes[0] < 2 * (uint64_t)kPrimes[1],
+              "Garner step assumes p1 < p0 < 2 p1");
+static_assert(kPrimes[0] < kPrimes[2] && kPrimes[1] < kPrimes[2],
+              "Garner step assumes p0, p1 < p2");
+static_assert((uint32_t)(kNegInv[0] * kPrimes[0]) == 0xFFFFFFFFu, "Montgomery constant");
+
+// ---------------------------------------------------------------------------
+// Canonical residues in [0, p), p < 2^31.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t fadd(uint32_t a, uint32_t b, uint32_t p)
+{
+    uint32_t s = a + b;          // < 2p < 2^32
+    return min(s, s - p);        // s - p wraps above s when s < p
+}
+
+__device__ __forceinline__ uint32_t fsub(uint32_t a, uint32_t b, uint32_t p)
+{
+    uint32_t d = a - b;          // wraps when a < b
+    return min(d, d + p);
+}
+
+// x w mod p for any 32-bit x, with wq = floor(w 2^32 / p) precomputed (Shoup).
+__device__ __forceinline__ uint32_t fmul_shoup(uint32_t x, uint32_t w, uint32_t wq, uint32_t p)
+{
+    uint32_t q = __umulhi(x, wq);
+    uint32_t r = x * w - q * p;  // in [0, 2p)
+    return min(r, r - p);
+}
+
+// a b 2^{-32} mod p (Montgomery reduction), a, b < p.
+__device__ __forceinline__ uint32_t fmul_mont(uint32_t a, uint32_t b, uint32_t p, uint32_t pneg)
+{
+    uint64_t t = (uint64_t)a * b;
+    uint32_t m = (uint32_t)t * pneg;
+    uint32_t u = (uint32_t)((t + (uint64_t)m * p) >> 32);  // < 2p
+    return min(u, u - p);
+}
+
+// v mod p for any 32-bit v (v < 3p for these primes).
+__device__ __forceinline__ uint32_t freduce32(uint32_t v, uint32_t p)
+{
+    v = min(v, v - p);
+    return min(v, v - p);
+}
+
+}  // namespace pa

@@ -1,0 +1,80 @@
+// Internal interface between the runtime and the kernels of libpa.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "field.h"
+
+namespace pa {
+
+constexpr int kTileLog = 12;                 // one LDS tile: 4096 residues
+constexpr int kTile = 1 << kTileLog;
+constexpr int kPassThreads = 256;
+
+// Device tables shared by every plan, one block per prime.
+struct Tables {
+    // (w, floor(w 2^32 / p)) for w = omega_4096^e, e < 4096: in-tile butterflies.
+    const uint2* tile_tw;     // [kNumPrimes][4096]
+    // Montgomery form of omega_{2^25}^i (i < 4096) and omega_{2^25}^{4096 j}
+    // (j < 8192): pass twiddles omega^E = lo[E & 4095] * hi[E >> 12].
+    const uint32_t* pass_lo;  // [kNumPrimes][4096]
+    const uint32_t* pass_hi;  // [kNumPrimes][8192]
+};
+
+enum Source : int {
+    kSrcArray = 0,   // residues already in `data`
+    kSrcDigits = 1,  // 32-bit digits of an n-bit operand in memory
+    kSrcSeed = 2,    // digits of the SplitMix64 stream of `seed`, bit 0 forced to 1
+};
+
+enum PassMode : int {
+    kForward = 0,    // load, DIF, post-twiddle, store (last pass: keep bit-reversed)
+    kInverse = 1,    // load, pre-twiddle, DIT, store natural order
+    kFused = 2,      // last forward pass of x, pointwise with c-hat, first inverse pass
+};
+
+// One LDS pass of a multi-pass transform over L = 2^logL points.  The array is
+// viewed as L / (R S) blocks of R rows by S contiguous columns (R = 2^r,
+// S = 2^s); the pass transforms along the rows of every column.
+struct PassArgs {
+    uint32_t* data;            // [kNumPrimes][L]
+    const uint32_t* other;     // kFused: pre-scaled c-hat, same layout
+    const uint32_t* digits;    // kSrcDigits: ceil(n/32) 32-bit digits
+    uint64_t seed;             // kSrcSeed
+    uint64_t n;                // operand bits (sources only)
+    uint32_t num_digits;       // ceil(n / 32)
+    int logL, r, s;
+    int mode, src;
+    int scale;                 // multiply the stored output by scale_w (Shoup)
+    uint32_t scale_w[kNumPrimes], scale_q[kNumPrimes];
+    Tables tb;
+};
+
+// Carry propagation, addend and bit extraction over the CRT-combined product.
+constexpr int kCarryThreads = 256;
+constexpr int kCarryPerThread = 16;
+constexpr int kCarryChunk = kCarryThreads * kCarryPerThread;   // digits per chunk
+
+struct CarryArgs {
+    const uint32_t* res;       // [kNumPrimes][L] residues of the product (natural order)
+    uint32_t L;
+    uint32_t num_digits;       // D = ceil(n / 32)
+    uint64_t n, m;
+    int addend_src;            // kSrcDigits or kSrcSeed (no forced odd bit)
+    const uint32_t* addend;    // kSrcDigits
+    uint64_t seed;             // kSrcSeed
+    uint8_t* desc;             // [chunks] carry-transfer function of each chunk
+    uint8_t* carry_in;         // [chunks]
+    uint32_t* value;           // [D] digits of V (only the top m bits' digits written)
+    uint64_t* out;             // ceil(m / 64) words
+    uint32_t chunks;
+};
+
+hipError_t launch_pass(const PassArgs& a, hipStream_t stream);
+hipError_t launch_carry_chunk(const CarryArgs& a, hipStream_t stream);
+hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream);
+hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream);
+hipError_t launch_extract(const CarryArgs& a, hipStream_t stream);
+
+}  // namespace pa

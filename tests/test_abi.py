@@ -1,0 +1,76 @@
+"""CPU-side checks of the C ABI library: it loads, exports every function the
+header declares, and its host-only helpers and argument checks behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pa.h")
+LIB = os.path.join(ROOT, "paper_1910_04429_amd", "libpa.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pa_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ["pa_init", "pa_destroy", "pa_strerror", "pa_last_error", "pa_hash",
+                 "pa_hash_ex", "pa_hash_async", "pa_hash_profile", "pa_reserve",
+                 "pa_workspace_bytes", "pa_transform_length"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_host_helpers():
+    import paper_1910_04429_amd as pa
+    # L = next power of two >= 2D - 1 (at least 64), D = ceil(n / 32)
+    assert pa.pa_transform_length(1) == 64
+    assert pa.pa_transform_length(1_000_000) == 1 << 16
+    assert pa.pa_transform_length(10_000_000) == 1 << 20
+    assert pa.pa_transform_length(100_000_000) == 1 << 23
+    assert pa.pa_transform_length(pa.PA_MAX_N) == 1 << 25
+    assert pa.pa_transform_length(pa.PA_MAX_N + 1) == 0
+    assert pa.pa_transform_length(0) == 0
+    assert pa.pa_workspace_bytes(100_000_000) >= 2 * 3 * 4 * (1 << 23)
+    assert pa.pa_strerror(pa.PA_EINVAL) == "invalid argument"
+
+
+def test_null_context_is_rejected():
+    lib = ctypes.CDLL(LIB)
+    lib.pa_hash.restype = ctypes.c_int
+    lib.pa_hash.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_uint64] * 4 + [ctypes.c_void_p]
+    assert lib.pa_hash(None, None, 0, 0, 64, 8, None) == 1   # PA_EINVAL
+    lib.pa_destroy.argtypes = [ctypes.c_void_p]
+    lib.pa_destroy(None)
+
+
+def test_product_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1910_04429_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower(), f
+
+
+def test_init_without_gpu_fails_cleanly():
+    import paper_1910_04429_amd as pa
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(pa.PAError) as e:
+        pa.pa_init(0)
+    assert e.value.status == pa.PA_ENODEV
