@@ -53,6 +53,13 @@ _u64 = ctypes.c_uint64
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+
+# libpa needs the HIP runtime by its soname (libamdhip64.so.7).  torch ships its
+# own copy under the same soname; loading torch first makes the dynamic linker
+# bind libpa to that one, so the process has a single HIP runtime and torch's
+# device pointers and streams are valid inside libpa.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 _lib.pa_init.restype = ctypes.c_int

@@ -5,6 +5,7 @@ import os
 import re
 
 import pytest
+import torch  # noqa: F401  (load torch's HIP runtime before libpa, as the binding does)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pa.h")
@@ -74,3 +75,11 @@ def test_init_without_gpu_fails_cleanly():
     with pytest.raises(pa.PAError) as e:
         pa.pa_init(0)
     assert e.value.status == pa.PA_ENODEV
+
+
+def test_single_hip_runtime_in_process():
+    """The binding must share torch's HIP runtime, not load a second one."""
+    import paper_1910_04429_amd  # noqa: F401
+    with open("/proc/self/maps") as f:
+        paths = {line.split()[-1] for line in f if "libamdhip64" in line}
+    assert len(paths) == 1, paths
