@@ -8,16 +8,16 @@
 
 namespace pa {
 
-constexpr int kTileLog = 12;                 // one LDS tile: 4096 residues
+constexpr int kTileLog = 14;                 // one LDS tile: 2^14 residues, 64 KB
 constexpr int kTile = 1 << kTileLog;
+constexpr int kStridedMaxLog = 9;            // strided passes: <= 512 rows x >= 32 columns
+constexpr int kMaxSteps = 4;
 constexpr int kPassThreads = 256;
 
 // Device tables shared by every plan, one block per prime.
 struct Tables {
-    // (w, floor(w 2^32 / p)) for w = omega_4096^e, e < 4096: in-tile butterflies.
-    const uint2* tile_tw;     // [kNumPrimes][4096]
     // Montgomery form of omega_{2^25}^i (i < 4096) and omega_{2^25}^{4096 j}
-    // (j < 8192): pass twiddles omega^E = lo[E & 4095] * hi[E >> 12].
+    // (j < 8192): any power omega^E = lo[E & 4095] * hi[E >> 12].
     const uint32_t* pass_lo;  // [kNumPrimes][4096]
     const uint32_t* pass_hi;  // [kNumPrimes][8192]
 };
@@ -36,15 +36,21 @@ enum PassMode : int {
 
 // One LDS pass of a multi-pass transform over L = 2^logL points.  The array is
 // viewed as L / (R S) blocks of R rows by S contiguous columns (R = 2^r,
-// S = 2^s); the pass transforms along the rows of every column.
+// S = 2^s); the pass transforms along the rows of every column.  A tile holds
+// 2^logN residues: R rows by 2^(logN - r) adjacent columns.  Inside the tile
+// the length-R transform runs as nsteps register steps of radix 2^steps[i].
 struct PassArgs {
     uint32_t* data;            // [kNumPrimes][L]
     const uint32_t* other;     // kFused: pre-scaled c-hat, same layout
     const uint32_t* digits;    // kSrcDigits: ceil(n/32) 32-bit digits
+    const uint2* rtw;          // [kNumPrimes][64]: (omega_64^{+-e}, Shoup quotient)
     uint64_t seed;             // kSrcSeed
     uint64_t n;                // operand bits (sources only)
     uint32_t num_digits;       // ceil(n / 32)
-    int logL, r, s;
+    uint32_t store_limit;      // positions >= this are not stored (L if all)
+    int logL, logN, r, s;
+    int nsteps;
+    int steps[kMaxSteps];
     int mode, src;
     int scale;                 // multiply the stored output by scale_w (Shoup)
     uint32_t scale_w[kNumPrimes], scale_q[kNumPrimes];

@@ -2,14 +2,29 @@
 //
 // The product c*x is a cyclic convolution of the two digit vectors padded to a
 // length L >= 2D - 1 (Alg. 1: fill zero, split, evaluate, pointwise multiply,
-// interpolate).  A length-L transform is done as a sequence of passes: pass i
-// takes length-R_i transforms down the rows of R_i x S_i blocks (S_i the
-// product of the later radices) and multiplies output row k of column c by
-// omega_{R_i S_i}^{c k}; the last pass (S = 1) works on contiguous blocks and
-// leaves them in bit-reversed order.  The inverse runs the passes in reverse
-// with inverse roots, pre-twiddles and decimation in time, so no explicit
-// reordering is ever done: both operands share the same scrambled spectrum
-// layout, which the pointwise product does not care about.
+// interpolate).  A length-L transform is a short sequence of passes; each pass
+// works on 64 KB LDS tiles (kTile residues of one prime) and reads and writes
+// its array once.
+//
+// Pass structure (decimation in frequency).  With the array seen as L/(R S)
+// blocks of R rows by S contiguous columns, a pass does a length-R transform
+// down every column and multiplies output row k of column j by omega_{RS}^{j k}.
+// The last pass has S = 1 (contiguous blocks of R); earlier passes take C
+// adjacent columns per tile so that every row segment is a full 128-byte line.
+//
+// Inside a tile the length-R transform is itself split into steps of radix
+// 2^r <= 64.  A step loads each of its small DFTs from LDS into registers, runs
+// the radix-2 butterflies there with the omega_64 powers (uniform across the
+// wavefront), multiplies output k by b^k for a per-DFT base b, and writes back.
+// For DIF step s on sub-blocks of size B split as n = n_s sigma + o the base is
+// omega_B^o; a strided pass also folds its omega_{RS}^{j k} factor into the
+// bases of its steps, so there is no separate twiddle sweep.
+//
+// Outputs stay in the digit-reversed order that the steps produce; the inverse
+// transform runs the same passes and steps backwards (decimation in time, with
+// inverse roots and pre-multiplication), so no explicit reordering is done:
+// both operands share the same scrambled spectrum, which the pointwise product
+// does not care about.
 #include "kernels.h"
 
 namespace pa {
@@ -24,9 +39,12 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
     return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits)
+constexpr int bitrev_c(int x, int bits)
 {
-    return bits == 0 ? 0u : (__brev(x) >> (32 - bits));
+    int r = 0;
+    for (int i = 0; i < bits; ++i)
+        r |= ((x >> i) & 1) << (bits - 1 - i);
+    return r;
 }
 
 // Digit t of the operand described by the pass source (0 beyond the top digit).
@@ -38,7 +56,7 @@ __device__ __forceinline__ uint32_t source_digit(const PassArgs& a, uint32_t t)
     if (a.src == kSrcDigits) {
         v = a.digits[t];
     } else {
-        uint64_t w = splitmix64(a.seed, t >> 1);
+        const uint64_t w = splitmix64(a.seed, t >> 1);
         v = (t & 1) ? (uint32_t)(w >> 32) : (uint32_t)w;
         if (t == 0)
             v |= 1u;  // the multiplier must be odd (eq. (6))
@@ -49,88 +67,181 @@ __device__ __forceinline__ uint32_t source_digit(const PassArgs& a, uint32_t t)
     return v;
 }
 
-// Montgomery form of omega_{2^25}^E.
-__device__ __forceinline__ uint32_t pass_twiddle(const Tables& tb, int pi, uint32_t E,
-                                                 uint32_t p, uint32_t pneg)
+// Montgomery form of omega_{2^25}^E, E < 2^25.
+__device__ __forceinline__ uint32_t root_pow(const Tables& tb, int pi, uint32_t E, uint32_t p,
+                                             uint32_t pneg)
 {
     const uint32_t lo = tb.pass_lo[pi * 4096 + (E & 4095u)];
     const uint32_t hi = tb.pass_hi[pi * 8192 + (E >> 12)];
     return fmul_mont(lo, hi, p, pneg);
 }
 
-// Radix-2 decimation-in-frequency transforms of length R = 2^r down the rows of
-// `ncols` columns held in LDS as (g, row, cc) -> (g R + row) C + cc, col = g C + cc.
-// Natural-order input, bit-reversed output.
-template <bool kInv>
-__device__ void lds_dif(uint32_t* sm, int r, int logC, int ncols, const uint2* tw, uint32_t p)
+// LDS index of tile element e: XOR of bits 2..5 with bits 8..11, a bijection
+// that keeps 4-element groups together and spreads the strided step accesses
+// over the banks.
+__device__ __forceinline__ uint32_t swz(uint32_t e) { return e ^ (((e >> 8) & 15u) << 2); }
+
+// Radix-2^R DIF butterflies in registers: natural input, bit-reversed output.
+// tw[e] = (omega_64^e, Shoup quotient), e < 32.
+template <int R>
+__device__ __forceinline__ void dif_regs(uint32_t* x, const uint2* __restrict__ tw, uint32_t p)
 {
-    const int halfR = (1 << r) >> 1;
-    const int total = ncols * halfR;
-    const bool colfast = logC >= 5;
-    const int C = 1 << logC;
-    for (int lh = r - 1; lh >= 0; --lh) {
+    constexpr int N = 1 << R;
+#pragma unroll
+    for (int lh = R - 1; lh >= 0; --lh) {
         const int h = 1 << lh;
-        const int tshift = kTileLog - 1 - lh;
-        for (int bi = threadIdx.x; bi < total; bi += blockDim.x) {
-            int col, j;
-            if (colfast) {
-                col = bi % ncols;
-                j = bi / ncols;
-            } else {
-                j = bi & (halfR - 1);
-                col = bi >> (r - 1);
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += 2 * h) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                const uint32_t a = x[i0 + j], b = x[i0 + j + h];
+                x[i0 + j] = fadd(a, b, p);
+                const uint32_t d = fsub(a, b, p);
+                if (j == 0) {
+                    x[i0 + j + h] = d;
+                } else {
+                    const uint2 w = tw[j << (5 - lh)];
+                    x[i0 + j + h] = fmul_shoup(d, w.x, w.y, p);
+                }
             }
-            const int g = col >> logC, cc = col & (C - 1);
-            const int jl = j & (h - 1);
-            const int i = ((j >> lh) << (lh + 1)) + jl;
-            uint32_t* base = sm + ((g << r) << logC) + cc;
-            const uint32_t x0 = base[i << logC], x1 = base[(i + h) << logC];
-            int e = jl << tshift;
-            if (kInv)
-                e = (kTile - e) & (kTile - 1);
-            const uint2 w = tw[e];
-            base[i << logC] = fadd(x0, x1, p);
-            base[(i + h) << logC] = fmul_shoup(fsub(x0, x1, p), w.x, w.y, p);
         }
-        __syncthreads();
     }
 }
 
-// Radix-2 decimation-in-time transforms, bit-reversed input, natural output.
-template <bool kInv>
-__device__ void lds_dit(uint32_t* sm, int r, int logC, int ncols, const uint2* tw, uint32_t p)
+// Radix-2^R DIT butterflies with inverse roots: bit-reversed input, natural
+// output.  tw[e] = (omega_64^{-e}, Shoup quotient).
+template <int R>
+__device__ __forceinline__ void dit_regs(uint32_t* x, const uint2* __restrict__ tw, uint32_t p)
 {
-    const int halfR = (1 << r) >> 1;
-    const int total = ncols * halfR;
-    const bool colfast = logC >= 5;
-    const int C = 1 << logC;
-    for (int lh = 0; lh < r; ++lh) {
+    constexpr int N = 1 << R;
+#pragma unroll
+    for (int lh = 0; lh < R; ++lh) {
         const int h = 1 << lh;
-        const int tshift = kTileLog - 1 - lh;
-        for (int bi = threadIdx.x; bi < total; bi += blockDim.x) {
-            int col, j;
-            if (colfast) {
-                col = bi % ncols;
-                j = bi / ncols;
-            } else {
-                j = bi & (halfR - 1);
-                col = bi >> (r - 1);
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += 2 * h) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                const uint32_t a = x[i0 + j];
+                uint32_t b = x[i0 + j + h];
+                if (j != 0) {
+                    const uint2 w = tw[j << (5 - lh)];
+                    b = fmul_shoup(b, w.x, w.y, p);
+                }
+                x[i0 + j] = fadd(a, b, p);
+                x[i0 + j + h] = fsub(a, b, p);
             }
-            const int g = col >> logC, cc = col & (C - 1);
-            const int jl = j & (h - 1);
-            const int i = ((j >> lh) << (lh + 1)) + jl;
-            uint32_t* base = sm + ((g << r) << logC) + cc;
-            int e = jl << tshift;
-            if (kInv)
-                e = (kTile - e) & (kTile - 1);
-            const uint2 w = tw[e];
-            const uint32_t x0 = base[i << logC];
-            const uint32_t x1 = fmul_shoup(base[(i + h) << logC], w.x, w.y, p);
-            base[i << logC] = fadd(x0, x1, p);
-            base[(i + h) << logC] = fsub(x0, x1, p);
         }
-        __syncthreads();
     }
+}
+
+// Geometry of one step inside a tile of R rows x C columns.
+struct StepGeo {
+    int logC;       // columns
+    int logSig;     // row stride of the DFT elements
+    int logB;       // sub-block rows = radix * stride
+    int inner;      // multiply by omega_B^{o k}
+    int colmul;     // multiply by omega_M^{j colmul k} (0: none)
+    int logM;       // pass block length R * S
+    uint32_t col0;  // global column of tile column 0
+};
+
+// One DIF (forward) or DIT (inverse) step of radix 2^R over every DFT of the tile.
+template <int R, bool kInv>
+__device__ void run_step(uint32_t* sm, int N, const StepGeo& g, const uint2* tw, const Tables& tb,
+                         int pi, uint32_t p, uint32_t pneg)
+{
+    constexpr int RHO = 1 << R;
+    const int ndft = N >> R;
+    const uint32_t cmask = (1u << g.logC) - 1u;
+    const uint32_t omask = (1u << g.logSig) - 1u;
+    const bool twiddle = g.inner || g.colmul;
+    for (int q = threadIdx.x; q < ndft; q += kPassThreads) {
+        const uint32_t c = (uint32_t)q & cmask;
+        const uint32_t o = ((uint32_t)q >> g.logC) & omask;
+        const uint32_t beta = (uint32_t)q >> (g.logC + g.logSig);
+        // element n of this DFT sits at row beta B + n sigma + o, column c
+        const uint32_t base = (((beta << g.logB) + o) << g.logC) + c;
+        const uint32_t nstep = 1u << (g.logSig + g.logC);
+        uint32_t x[RHO];
+        uint32_t b = 0;  // Montgomery form of the twiddle base
+        if (twiddle) {
+            uint32_t E = 0;
+            if (g.inner) E += o << (kLogMaxLen - g.logB);
+            if (g.colmul) E += ((g.col0 + c) * (uint32_t)g.colmul) << (kLogMaxLen - g.logM);
+            E &= (1u << kLogMaxLen) - 1u;
+            if (kInv) E = (0u - E) & ((1u << kLogMaxLen) - 1u);
+            b = root_pow(tb, pi, E, p, pneg);
+        }
+        if (!kInv) {
+#pragma unroll
+            for (int n = 0; n < RHO; ++n)
+                x[n] = sm[swz(base + n * nstep)];
+            dif_regs<R>(x, tw, p);
+            if (twiddle) {
+                uint32_t w = b;
+#pragma unroll
+                for (int k = 1; k < RHO; ++k) {
+                    const int j = bitrev_c(k, R);
+                    x[j] = fmul_mont(x[j], w, p, pneg);
+                    if (k + 1 < RHO) w = fmul_mont(w, b, p, pneg);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < RHO; ++j)
+                sm[swz(base + bitrev_c(j, R) * nstep)] = x[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < RHO; ++j)
+                x[j] = sm[swz(base + bitrev_c(j, R) * nstep)];
+            if (twiddle) {
+                uint32_t w = b;
+#pragma unroll
+                for (int k = 1; k < RHO; ++k) {
+                    const int j = bitrev_c(k, R);
+                    x[j] = fmul_mont(x[j], w, p, pneg);
+                    if (k + 1 < RHO) w = fmul_mont(w, b, p, pneg);
+                }
+            }
+            dit_regs<R>(x, tw, p);
+#pragma unroll
+            for (int n = 0; n < RHO; ++n)
+                sm[swz(base + n * nstep)] = x[n];
+        }
+    }
+}
+
+template <bool kInv>
+__device__ void dispatch_step(int r, uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
+                              const Tables& tb, int pi, uint32_t p, uint32_t pneg)
+{
+    switch (r) {
+    case 1: run_step<1, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
+    case 2: run_step<2, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
+    case 3: run_step<3, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
+    case 4: run_step<4, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
+    case 5: run_step<5, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
+    case 6: run_step<6, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
+    default: break;
+    }
+}
+
+// Geometry of step s of a pass with the given radix split.
+__device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int logC, int s, uint32_t col0)
+{
+    int above = 0;
+    for (int i = 0; i < s; ++i) above += a.steps[i];
+    const int logB = a.r - above;
+    StepGeo g;
+    g.logC = logC;
+    g.logB = logB;
+    g.logSig = logB - a.steps[s];
+    g.inner = (s + 1 < a.nsteps);
+    g.logM = a.r + a.s;
+    g.col0 = col0;
+    // the pass factor omega_M^{j k}, k = k_0 + rho_0 k_1: step 0 takes
+    // omega_M^{j k_0}, step 1 (strided passes have at most two) omega_M^{j rho_0 k_1}
+    g.colmul = (a.s > 0) ? (s == 0 ? 1 : (1 << a.steps[0])) : 0;
+    return g;
 }
 
 __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
@@ -139,79 +250,101 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
 
     const int pi = blockIdx.y;
     const uint32_t p = kPrimes[pi], pneg = kNegInv[pi];
-    const uint2* tw = a.tb.tile_tw + pi * kTile;
+    const uint2* twf = a.rtw + pi * 64;       // omega_64^e, e < 32
+    const uint2* twi = twf + 32;              // omega_64^{-e}
     uint32_t* data = a.data + ((size_t)pi << a.logL);
 
-    const int logT = min(kTileLog, a.logL);
-    const int T = 1 << logT;
-    const int r = a.r, s = a.s;
-    const int logC = min(s, logT - r);
-    const int logG = logT - r - logC;
-    const int C = 1 << logC;
-    const int logM = r + s;
-    const int logCgs = s - logC;                 // column groups per block
-    const int bg = blockIdx.x >> logCgs;
-    const int cg = blockIdx.x & ((1 << logCgs) - 1);
-    const int ncols = 1 << (logG + logC);
-    const int twshift = kLogMaxLen - logM;
+    const int logN = a.logN;                  // tile residues
+    const int N = 1 << logN;
+    const int logC = logN - a.r;              // columns per tile
+    const int logCgs = a.s - logC;            // column groups per block
+    const uint32_t bg = blockIdx.x >> logCgs;
+    const uint32_t col0 = (blockIdx.x & ((1u << logCgs) - 1u)) << logC;
+    const uint32_t blk0 = bg << (a.r + a.s); // global offset of the block
 
-    // ---- load ----
-    for (int li = threadIdx.x; li < T; li += kPassThreads) {
-        const int cc = li & (C - 1);
-        const int row = (li >> logC) & ((1 << r) - 1);
-        const int g = li >> (r + logC);
-        const uint32_t col = (uint32_t)(cg << logC) + cc;
-        const uint32_t pos = ((uint32_t)((bg << logG) + g) << logM) + ((uint32_t)row << s) + col;
-        if (a.mode == kInverse) {
-            uint32_t v = data[pos];
-            if (s > 0) {
-                uint32_t E = (col * (uint32_t)row) << twshift;
-                E = (0u - E) & ((1u << kLogMaxLen) - 1u);
-                v = fmul_mont(v, pass_twiddle(a.tb, pi, E, p, pneg), p, pneg);
-            }
-            sm[(((g << r) + (int)bitrev(row, r)) << logC) + cc] = v;
+    // Tile element (row, c) <-> global position blk0 + row S + col0 + c; moved
+    // in groups of 4 consecutive columns (C >= 4) or rows (C == 1).
+    const int nq = N >> 2;
+    for (int u = threadIdx.x; u < nq; u += kPassThreads) {
+        uint32_t e, pos;
+        if (logC >= 2) {
+            const uint32_t row = (uint32_t)u >> (logC - 2);
+            const uint32_t c = ((uint32_t)u << 2) & ((1u << logC) - 1u);
+            e = (row << logC) + c;
+            pos = blk0 + (row << a.s) + col0 + c;
         } else {
-            sm[li] = (a.src == kSrcArray) ? data[pos] : freduce32(source_digit(a, pos), p);
+            e = (uint32_t)u << 2;
+            pos = blk0 + e;
         }
+        uint4 v;
+        if (a.src == kSrcArray) {
+            v = *reinterpret_cast<const uint4*>(data + pos);
+        } else {
+            v.x = freduce32(source_digit(a, pos + 0), p);
+            v.y = freduce32(source_digit(a, pos + 1), p);
+            v.z = freduce32(source_digit(a, pos + 2), p);
+            v.w = freduce32(source_digit(a, pos + 3), p);
+        }
+        *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
     }
     __syncthreads();
 
-    // ---- transform ----
     if (a.mode == kInverse) {
-        lds_dit<true>(sm, r, logC, ncols, tw, p);
+        for (int s = a.nsteps - 1; s >= 0; --s) {
+            const StepGeo g = step_geo(a, logC, s, col0);
+            dispatch_step<true>(a.steps[s], sm, N, g, twi, a.tb, pi, p, pneg);
+            __syncthreads();
+        }
     } else {
-        lds_dif<false>(sm, r, logC, ncols, tw, p);
+        for (int s = 0; s < a.nsteps; ++s) {
+            const StepGeo g = step_geo(a, logC, s, col0);
+            dispatch_step<false>(a.steps[s], sm, N, g, twf, a.tb, pi, p, pneg);
+            __syncthreads();
+        }
         if (a.mode == kFused) {
-            // Pointwise product with the pre-scaled c-hat (stored in the same
-            // bit-reversed block layout), then the inverse of this pass.
+            // Pointwise product with the pre-scaled c-hat (same layout), then
+            // the inverse of this pass.
             const uint32_t* other = a.other + ((size_t)pi << a.logL);
-            for (int li = threadIdx.x; li < T; li += kPassThreads) {
-                const uint32_t pos = ((uint32_t)((bg << logG)) << logM) + (uint32_t)li;
-                sm[li] = fmul_mont(sm[li], other[pos], p, pneg);
+            for (int u = threadIdx.x; u < nq; u += kPassThreads) {
+                const uint32_t e = (uint32_t)u << 2;
+                const uint4 cv = *reinterpret_cast<const uint4*>(other + blk0 + e);
+                uint4 v = *reinterpret_cast<uint4*>(&sm[swz(e)]);
+                v.x = fmul_mont(v.x, cv.x, p, pneg);
+                v.y = fmul_mont(v.y, cv.y, p, pneg);
+                v.z = fmul_mont(v.z, cv.z, p, pneg);
+                v.w = fmul_mont(v.w, cv.w, p, pneg);
+                *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
             }
             __syncthreads();
-            lds_dit<true>(sm, r, logC, ncols, tw, p);
+            for (int s = a.nsteps - 1; s >= 0; --s) {
+                const StepGeo g = step_geo(a, logC, s, col0);
+                dispatch_step<true>(a.steps[s], sm, N, g, twi, a.tb, pi, p, pneg);
+                __syncthreads();
+            }
         }
     }
 
-    // ---- store ----
-    for (int li = threadIdx.x; li < T; li += kPassThreads) {
-        const int cc = li & (C - 1);
-        const int row = (li >> logC) & ((1 << r) - 1);
-        const int g = li >> (r + logC);
-        const uint32_t col = (uint32_t)(cg << logC) + cc;
-        const uint32_t pos = ((uint32_t)((bg << logG) + g) << logM) + ((uint32_t)row << s) + col;
-        uint32_t v;
-        if (a.mode == kForward && s > 0) {
-            v = sm[(((g << r) + (int)bitrev(row, r)) << logC) + cc];
-            const uint32_t E = (col * (uint32_t)row) << twshift;
-            v = fmul_mont(v, pass_twiddle(a.tb, pi, E, p, pneg), p, pneg);
+    for (int u = threadIdx.x; u < nq; u += kPassThreads) {
+        uint32_t e, pos;
+        if (logC >= 2) {
+            const uint32_t row = (uint32_t)u >> (logC - 2);
+            const uint32_t c = ((uint32_t)u << 2) & ((1u << logC) - 1u);
+            e = (row << logC) + c;
+            pos = blk0 + (row << a.s) + col0 + c;
         } else {
-            v = sm[li];
+            e = (uint32_t)u << 2;
+            pos = blk0 + e;
         }
-        if (a.scale)
-            v = fmul_shoup(v, a.scale_w[pi], a.scale_q[pi], p);
-        data[pos] = v;
+        uint4 v = *reinterpret_cast<const uint4*>(&sm[swz(e)]);
+        if (a.scale) {
+            const uint32_t w = a.scale_w[pi], q = a.scale_q[pi];
+            v.x = fmul_shoup(v.x, w, q, p);
+            v.y = fmul_shoup(v.y, w, q, p);
+            v.z = fmul_shoup(v.z, w, q, p);
+            v.w = fmul_shoup(v.w, w, q, p);
+        }
+        if (pos < a.store_limit)
+            *reinterpret_cast<uint4*>(data + pos) = v;
     }
 }
 
@@ -219,8 +352,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t stream)
 {
-    const int logT = a.logL < kTileLog ? a.logL : kTileLog;
-    const unsigned tiles = 1u << (a.logL - logT);
+    const unsigned tiles = 1u << (a.logL - a.logN);
     hipLaunchKernelGGL(k_pass, dim3(tiles, kNumPrimes), dim3(kPassThreads), 0, stream, a);
     return hipGetLastError();
 }

@@ -13,7 +13,7 @@ struct pa_ctx {
     int device = 0;
     hipStream_t stream = nullptr;     // used by the synchronous entry points
     // tables
-    uint2* tile_tw = nullptr;
+    uint2* rtw = nullptr;
     uint32_t* pass_lo = nullptr;
     uint32_t* pass_hi = nullptr;
     // workspace, sized for cap_L / cap_D
@@ -107,8 +107,8 @@ int log2_len(uint64_t n)
 
 uint32_t chunks_of(uint64_t D) { return (uint32_t)((D + kCarryChunk - 1) / kCarryChunk); }
 
-// Passes of a length-2^l transform: up to 6-bit strided passes, then one
-// contiguous pass of up to 12 bits.
+// Passes of a length-2^l transform: strided passes of at most 2^9 rows, then
+// one contiguous pass of up to 2^14 points (a whole LDS tile).
 int plan_passes(int l, int* r)
 {
     if (l <= kTileLog) {
@@ -116,11 +116,23 @@ int plan_passes(int l, int* r)
         return 1;
     }
     const int head = l - kTileLog;
-    const int k = (head + 5) / 6;
+    const int k = (head + kStridedMaxLog - 1) / kStridedMaxLog;
     for (int i = 0; i < k; ++i)
         r[i] = head / k + (i < head % k ? 1 : 0);
     r[k] = kTileLog;
     return k + 1;
+}
+
+// Register steps of a length-2^r in-tile transform: radix 64 first, then the rest.
+int plan_steps(int r, int* st)
+{
+    int k = 0;
+    while (r > 6) {
+        st[k++] = 6;
+        r -= 6;
+    }
+    st[k++] = r;
+    return k;
 }
 
 void free_workspace(pa_ctx* ctx)
@@ -228,6 +240,8 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     const uint32_t D = (uint32_t)digits_of(n);
     int r[8];
     const int P = plan_passes(l, r);
+    for (int i = 0; i + 1 < P; ++i)   // strided tiles need >= 32 columns
+        if (kTileLog - r[i] < 5) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     int s[8];
     {
         int rem = l;
@@ -236,7 +250,7 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
             s[i] = rem;
         }
     }
-    Tables tb{ctx->tile_tw, ctx->pass_lo, ctx->pass_hi};
+    Tables tb{ctx->pass_lo, ctx->pass_hi};
     const uint64_t arr = kNumPrimes * 4ull * L;        // one residue array
     const uint64_t outD = kNumPrimes * 4ull * D;       // the product coefficients kept
 
@@ -244,15 +258,23 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     base.num_digits = D;
     base.n = n;
     base.logL = l;
+    base.logN = l < kTileLog ? l : kTileLog;
     base.tb = tb;
+    base.rtw = ctx->rtw;
+    base.store_limit = (uint32_t)L;
+    auto geometry = [&](PassArgs& a, int i) {
+        a.r = r[i];
+        a.s = s[i];
+        a.nsteps = plan_steps(r[i], a.steps);
+    };
+    const uint32_t limit = (uint32_t)((D + 3) & ~3ull);   // product digits kept
 
     // c-hat, scaled on its last pass by 2^32 / L so that the Montgomery
     // pointwise product yields x-hat c-hat / L.
     for (int i = 0; i < P; ++i) {
         PassArgs a = base;
         a.data = ctx->A;
-        a.r = r[i];
-        a.s = s[i];
+        geometry(a, i);
         a.mode = kForward;
         a.src = kSrcArray;
         if (i == 0) {
@@ -280,9 +302,9 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     for (int i = 0; i < P; ++i) {
         PassArgs a = base;
         a.data = ctx->B;
-        a.r = r[i];
-        a.s = s[i];
+        geometry(a, i);
         a.mode = (i == P - 1) ? kFused : kForward;
+        if (P == 1) a.store_limit = limit;
         a.other = ctx->A;
         a.src = (i == 0) ? kSrcDigits : kSrcArray;
         a.digits = reinterpret_cast<const uint32_t*>(d_key);
@@ -298,10 +320,10 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     for (int i = P - 2; i >= 0; --i) {
         PassArgs a = base;
         a.data = ctx->B;
-        a.r = r[i];
-        a.s = s[i];
+        geometry(a, i);
         a.mode = kInverse;
         a.src = kSrcArray;
+        if (i == 0) a.store_limit = limit;
         PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, arr + (i == 0 ? outD : arr), launch_pass(a, stream));
     }
     CarryArgs ca{};
@@ -387,7 +409,7 @@ int pa_init(pa_ctx** out, int device)
             rc = PA_EDEVICE;
             break;
         }
-        h_tile = new (std::nothrow) uint2[kNumPrimes * kTile];
+        h_tile = new (std::nothrow) uint2[kNumPrimes * 64];
         h_lo = new (std::nothrow) uint32_t[kNumPrimes * 4096];
         h_hi = new (std::nothrow) uint32_t[kNumPrimes * 8192];
         if (!h_tile || !h_lo || !h_hi) { rc = PA_ENOMEM; break; }
@@ -395,13 +417,14 @@ int pa_init(pa_ctx** out, int device)
             const uint64_t p = kPrimes[pi];
             const uint64_t g = generator(p);
             const uint64_t w25 = hpow(g, (p - 1) >> kLogMaxLen, p);   // order 2^25
-            const uint64_t w12 = hpow(w25, 1ull << (kLogMaxLen - kTileLog), p);
-            uint64_t w = 1;
-            for (int e = 0; e < kTile; ++e) {
-                h_tile[pi * kTile + e] = make_uint2((uint32_t)w, hshoup(w, p));
-                w = w * w12 % p;
+            const uint64_t w6 = hpow(w25, 1ull << (kLogMaxLen - 6), p);     // order 64
+            const uint64_t w6i = hpow(w6, p - 2, p);
+            for (int e = 0; e < 32; ++e) {
+                const uint64_t f = hpow(w6, e, p), b = hpow(w6i, e, p);
+                h_tile[pi * 64 + e] = make_uint2((uint32_t)f, hshoup(f, p));
+                h_tile[pi * 64 + 32 + e] = make_uint2((uint32_t)b, hshoup(b, p));
             }
-            w = 1;
+            uint64_t w = 1;
             for (int i = 0; i < 4096; ++i) {
                 h_lo[pi * 4096 + i] = hmont(w, p);
                 w = w * w25 % p;
@@ -413,13 +436,13 @@ int pa_init(pa_ctx** out, int device)
                 w = w * step % p;
             }
         }
-        if (hipMalloc(&ctx->tile_tw, sizeof(uint2) * kNumPrimes * kTile) != hipSuccess ||
+        if (hipMalloc(&ctx->rtw, sizeof(uint2) * kNumPrimes * 64) != hipSuccess ||
             hipMalloc(&ctx->pass_lo, sizeof(uint32_t) * kNumPrimes * 4096) != hipSuccess ||
             hipMalloc(&ctx->pass_hi, sizeof(uint32_t) * kNumPrimes * 8192) != hipSuccess) {
             rc = PA_ENOMEM;
             break;
         }
-        if (hipMemcpy(ctx->tile_tw, h_tile, sizeof(uint2) * kNumPrimes * kTile,
+        if (hipMemcpy(ctx->rtw, h_tile, sizeof(uint2) * kNumPrimes * 64,
                       hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(ctx->pass_lo, h_lo, sizeof(uint32_t) * kNumPrimes * 4096,
                       hipMemcpyHostToDevice) != hipSuccess ||
@@ -450,7 +473,7 @@ void pa_destroy(pa_ctx* ctx)
     (void)hipFree(ctx->d_out);
     (void)hipFree(ctx->d_c);
     (void)hipFree(ctx->d_d);
-    (void)hipFree(ctx->tile_tw);
+    (void)hipFree(ctx->rtw);
     (void)hipFree(ctx->pass_lo);
     (void)hipFree(ctx->pass_hi);
     if (ctx->have_events)
