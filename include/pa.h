@@ -108,10 +108,9 @@ int pa_hash_async(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_t 
 #define PA_PROFILE_MAX 32
 enum pa_kernel_kind {
     PA_K_NTT_PASS = 0,    /* one LDS pass of a forward, fused or inverse NTT */
-    PA_K_CARRY_CHUNK = 1, /* CRT + column sums + per-chunk carry function */
-    PA_K_CARRY_SCAN = 2,  /* carry into every chunk */
-    PA_K_CARRY_APPLY = 3, /* CRT + carry resolve + digits of V */
-    PA_K_EXTRACT = 4,     /* bits [n-m, n) of V into output words */
+    PA_K_CARRY_LOCAL = 1, /* CRT + addend + column sums -> carry function per chunk */
+    PA_K_CARRY_SCAN = 2,  /* carry entering every chunk */
+    PA_K_CARRY_APPLY = 3, /* CRT + addend + carry resolve + mod 2^n + top-m bits */
 };
 typedef struct pa_profile {
     int count;

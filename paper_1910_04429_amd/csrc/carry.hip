@@ -1,4 +1,4 @@
-// CRT, carry propagation, addend, mod 2^n and top-m extraction.
+// CRT, carry propagation, addend, mod 2^n and top-m extraction in one pass.
 //
 // After the inverse transform, position k < D holds the convolution
 // coefficient z_k = sum_{i+j=k} x_i c_j modulo each prime.  Garner's CRT turns
@@ -11,9 +11,17 @@
 //
 // with carry_0 = 0 and every carry in [0, 3].  Digits k >= D are discarded
 // (mod 2^n), the top digit is masked to n bits, and bits [n - m, n) of V are the
-// output.  The carry chain is resolved as a scan of carry-transfer functions
-// f_k : {0..3} -> {0..3}, f_k(c) = (s_k + c) >> 32, packed 2 bits per input in
-// one byte; composition is associative, so chunks and threads scan in parallel.
+// output.  The chain is a scan of carry-transfer functions f_k : {0..3} ->
+// {0..3}, f_k(c) = (s_k + c) >> 32, packed 2 bits per input in one byte;
+// composition is associative.
+//
+// Three launches, none of which waits on another workgroup: (1) every chunk of
+// digits stages its residues in LDS with coalesced loads, forms its column
+// sums and scans its threads' carry functions into the chunk's function;
+// (2) one workgroup scans the chunk functions into the carry entering each
+// chunk; (3) every chunk redoes (1), resolves its digits (and two past its end)
+// from its carry-in and writes every output word that starts inside the chunk.
+// Workgroups on different XCDs never exchange data inside a kernel.
 #include "kernels.h"
 
 namespace pa {
@@ -67,12 +75,11 @@ __device__ __forceinline__ uint32_t addend_digit(const CarryArgs& a, uint32_t t)
     return v;
 }
 
-// Exact coefficient z_k from its residues (Garner).  k < D <= L.
-__device__ __forceinline__ void crt(const uint32_t* res, uint32_t L, uint32_t k, uint32_t& z0,
+// Exact coefficient from its three residues (Garner).
+__device__ __forceinline__ void crt(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t& z0,
                                     uint32_t& z1, uint32_t& z2)
 {
     constexpr uint32_t p0 = kPrimes[0], p1 = kPrimes[1], p2 = kPrimes[2];
-    const uint32_t r0 = res[k], r1 = res[L + k], r2 = res[2 * (size_t)L + k];
     const uint32_t v0 = r0;
     const uint32_t v1 = fmul_mont(fsub(r1, min(v0, v0 - p1), p1), kInvP0ModP1M, p1, kNegInv[1]);
     const uint32_t t = fsub(r2, v0, p2);
@@ -88,147 +95,192 @@ __device__ __forceinline__ void crt(const uint32_t* res, uint32_t L, uint32_t k,
     z2 = (uint32_t)hi;
 }
 
-// Column sums s_k for this thread's kCarryPerThread digits starting at k0.
-__device__ void column_sums(const CarryArgs& a, uint32_t k0, uint64_t* s)
+// Chunk-local digit i in [-2, kChunk + 2) <-> LDS slot, padded so that
+// threads reading consecutive runs of kPer digits hit distinct banks.
+template <int kPer>
+__device__ __forceinline__ int slot(int i)
 {
-    uint32_t zm1_1 = 0, zm1_2 = 0, zm2_2 = 0;   // mid/hi words of z_{k-1}, hi of z_{k-2}
-    // Halo: z_{k0-2} and z_{k0-1}.
-    if (k0 >= 2) {
-        uint32_t a0, a1, a2;
-        crt(a.res, a.L, k0 - 2, a0, a1, a2);
-        zm2_2 = a2;
-    }
-    if (k0 >= 1) {
-        uint32_t a0, a1, a2;
-        crt(a.res, a.L, k0 - 1, a0, a1, a2);
-        zm1_1 = a1;
-        zm1_2 = a2;
-        // z_{k0-1} is k-1 for digit k0, and k-2 for digit k0+1
-    }
-    uint32_t prev_mid = zm1_1, prev_hi = zm1_2, prev2_hi = zm2_2;
-    for (int i = 0; i < kCarryPerThread; ++i) {
-        const uint32_t k = k0 + i;
-        if (k >= a.num_digits) {
-            s[i] = 0;
-            continue;
-        }
-        uint32_t z0, z1, z2;
-        crt(a.res, a.L, k, z0, z1, z2);
-        s[i] = (uint64_t)z0 + prev_mid + prev2_hi + addend_digit(a, k);
-        prev2_hi = prev_hi;
-        prev_mid = z1;
-        prev_hi = z2;
-    }
+    const int j = i + 2;
+    return j + j / kPer;
 }
 
-// Inclusive scan of carry functions over the block, in thread order.
-__device__ uint32_t block_scan_inclusive(uint32_t f, uint32_t* sh)
+// kApply = false: write the chunk's carry function.  kApply = true: resolve the
+// chunk with its carry-in and write its output words.
+template <int kPer, bool kApply>
+__global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
 {
-    sh[threadIdx.x] = f;
+    constexpr int kChunk = kCarryThreads * kPer;
+    constexpr int kSpan = kChunk + 4;                      // digits -2 .. kChunk+1
+    constexpr int kSlots = kSpan + kSpan / kPer + 1;
+    __shared__ uint32_t res[kNumPrimes][kSlots];
+    __shared__ uint32_t val[kSlots];
+    __shared__ uint32_t scan[kCarryThreads];
+
+    const int tid = threadIdx.x;
+    const uint32_t chunk = blockIdx.x;
+    const int64_t k0 = (int64_t)chunk * kChunk;
+    const uint32_t D = a.num_digits;
+
+    // residues of digits k0-2 .. k0+kChunk+1 (0 outside [0, D))
+    for (int i = tid; i < kSpan; i += kCarryThreads) {
+        const int64_t k = k0 - 2 + i;
+        const bool in = k >= 0 && k < (int64_t)D;
+#pragma unroll
+        for (int pi = 0; pi < kNumPrimes; ++pi)
+            res[pi][slot<kPer>(i - 2)] = in ? a.res[(size_t)pi * a.L + (size_t)k] : 0u;
+    }
     __syncthreads();
-    for (int d = 1; d < (int)blockDim.x; d <<= 1) {
-        uint32_t prev = (threadIdx.x >= (unsigned)d) ? sh[threadIdx.x - d] : kIdentity;
+
+    // column sums of this thread's kPer digits (and, for the last thread, the
+    // two digits past the chunk, which it resolves with the chunk's carry-out)
+    constexpr int kExtra = 2;
+    uint64_t s[kPer + kExtra];
+    const int first = tid * kPer;
+    const int count = kPer + (tid == kCarryThreads - 1 ? kExtra : 0);
+    {
+        uint32_t z0, z1, z2;
+        crt(res[0][slot<kPer>(first - 2)], res[1][slot<kPer>(first - 2)],
+            res[2][slot<kPer>(first - 2)], z0, z1, z2);
+        uint32_t prev2_hi = z2;
+        crt(res[0][slot<kPer>(first - 1)], res[1][slot<kPer>(first - 1)],
+            res[2][slot<kPer>(first - 1)], z0, z1, z2);
+        uint32_t prev_mid = z1, prev_hi = z2;
+#pragma unroll
+        for (int i = 0; i < kPer + kExtra; ++i) {
+            if (i < count) {
+                const int li = first + i;
+                crt(res[0][slot<kPer>(li)], res[1][slot<kPer>(li)], res[2][slot<kPer>(li)], z0,
+                    z1, z2);
+                const int64_t k = k0 + li;
+                const uint32_t d = (k < (int64_t)D) ? addend_digit(a, (uint32_t)k) : 0u;
+                s[i] = (k < (int64_t)D) ? (uint64_t)z0 + prev_mid + prev2_hi + d : 0ull;
+                prev2_hi = prev_hi;
+                prev_mid = z1;
+                prev_hi = z2;
+            }
+        }
+    }
+    uint32_t f = kIdentity;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+        f = compose(f, digit_function(s[i]));
+
+    // inclusive scan of the thread functions in thread order
+    scan[tid] = f;
+    __syncthreads();
+    for (int d = 1; d < kCarryThreads; d <<= 1) {
+        const uint32_t prev = (tid >= d) ? scan[tid - d] : kIdentity;
         __syncthreads();
         f = compose(prev, f);
-        sh[threadIdx.x] = f;
+        scan[tid] = f;
         __syncthreads();
     }
-    return f;
+
+    if (!kApply) {
+        if (tid == kCarryThreads - 1)
+            a.desc[chunk] = f;
+        return;
+    }
+    const uint32_t cin_chunk = a.carry_in[chunk];
+
+    // resolve this thread's digits; V digits of the chunk (and two past it) to LDS
+    uint64_t carry = tid ? apply(scan[tid - 1], cin_chunk) : cin_chunk;
+    const uint32_t top = (uint32_t)(a.n & 31);
+#pragma unroll
+    for (int i = 0; i < kPer + kExtra; ++i) {
+        if (i < count) {
+            const int li = first + i;
+            const int64_t k = k0 + li;
+            const uint64_t t = s[i] + carry;
+            uint32_t v = (uint32_t)t;
+            carry = t >> 32;
+            if (k >= (int64_t)D)
+                v = 0;
+            else if (k == (int64_t)D - 1 && top)
+                v &= (1u << top) - 1u;
+            val[slot<kPer>(li)] = v;
+        }
+    }
+    __syncthreads();
+
+    // output words whose first bit lies in this chunk: word j starts at bit
+    // b_j = n - m + 64 j, in digit b_j / 32
+    const uint64_t words = (a.m + 63) >> 6;
+    const uint64_t base = a.n - a.m;
+    const uint64_t lo_bit = (uint64_t)k0 * 32, hi_bit = lo_bit + (uint64_t)kChunk * 32;
+    const uint64_t j_lo = lo_bit > base ? (lo_bit - base + 63) >> 6 : 0;
+    uint64_t j_hi = hi_bit > base ? (hi_bit - base + 63) >> 6 : 0;
+    if (j_hi > words) j_hi = words;
+    for (uint64_t j = j_lo + tid; j < j_hi; j += kCarryThreads) {
+        const uint64_t bit = base + 64 * j;
+        const int q = (int)((bit >> 5) - (uint64_t)k0);   // in [0, kChunk)
+        const uint32_t sh = (uint32_t)(bit & 31);
+        const uint64_t v0 = val[slot<kPer>(q)], v1 = val[slot<kPer>(q + 1)],
+                       v2 = val[slot<kPer>(q + 2)];
+        uint64_t w = (v0 | (v1 << 32)) >> sh;
+        if (sh) w |= v2 << (64 - sh);
+        if (j == words - 1 && (a.m & 63))
+            w &= (1ull << (a.m & 63)) - 1ull;
+        a.out[j] = w;
+    }
 }
 
-__global__ __launch_bounds__(kCarryThreads) void k_carry_chunk(CarryArgs a)
-{
-    __shared__ uint32_t sh[kCarryThreads];
-    const uint32_t k0 = blockIdx.x * kCarryChunk + threadIdx.x * kCarryPerThread;
-    uint64_t s[kCarryPerThread];
-    column_sums(a, k0, s);
-    uint32_t f = kIdentity;
-    for (int i = 0; i < kCarryPerThread; ++i)
-        f = compose(f, digit_function(s[i]));
-    f = block_scan_inclusive(f, sh);
-    if (threadIdx.x == kCarryThreads - 1)
-        a.desc[blockIdx.x] = (uint8_t)f;
-}
-
-// One block: carry into every chunk from the chunk functions.
+// One workgroup: the carry into every chunk from the chunk functions.
 __global__ __launch_bounds__(1024) void k_carry_scan(CarryArgs a)
 {
     __shared__ uint32_t sh[1024];
+    const int tid = threadIdx.x;
     const uint32_t per = (a.chunks + 1023) / 1024;
-    const uint32_t j0 = threadIdx.x * per;
+    const uint32_t j0 = tid * per;
     uint32_t f = kIdentity;
     for (uint32_t j = j0; j < j0 + per && j < a.chunks; ++j)
         f = compose(f, a.desc[j]);
-    const uint32_t incl = block_scan_inclusive(f, sh);
+    sh[tid] = f;
     __syncthreads();
-    sh[threadIdx.x] = incl;
-    __syncthreads();
-    uint32_t c = threadIdx.x ? apply(sh[threadIdx.x - 1], 0) : 0u;
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t prev = (tid >= d) ? sh[tid - d] : kIdentity;
+        __syncthreads();
+        f = compose(prev, f);
+        sh[tid] = f;
+        __syncthreads();
+    }
+    uint32_t c = tid ? apply(sh[tid - 1], 0) : 0u;
     for (uint32_t j = j0; j < j0 + per && j < a.chunks; ++j) {
-        a.carry_in[j] = (uint8_t)c;
+        a.carry_in[j] = c;
         c = apply(a.desc[j], c);
     }
 }
 
-__global__ __launch_bounds__(kCarryThreads) void k_carry_apply(CarryArgs a)
-{
-    __shared__ uint32_t sh[kCarryThreads];
-    const uint32_t k0 = blockIdx.x * kCarryChunk + threadIdx.x * kCarryPerThread;
-    uint64_t s[kCarryPerThread];
-    column_sums(a, k0, s);
-    uint32_t f = kIdentity;
-    for (int i = 0; i < kCarryPerThread; ++i)
-        f = compose(f, digit_function(s[i]));
-    const uint32_t incl = block_scan_inclusive(f, sh);
-    __syncthreads();
-    sh[threadIdx.x] = incl;
-    __syncthreads();
-    const uint32_t cin_chunk = a.carry_in[blockIdx.x];
-    uint64_t carry = threadIdx.x ? apply(sh[threadIdx.x - 1], cin_chunk) : cin_chunk;
+}  // namespace
 
-    const uint32_t first = (uint32_t)((a.n - a.m) >> 5);   // lowest digit of the output
-    const uint32_t top = (uint32_t)(a.n & 31);
-    for (int i = 0; i < kCarryPerThread; ++i) {
-        const uint32_t k = k0 + i;
-        if (k >= a.num_digits)
-            break;
-        const uint64_t t = s[i] + carry;
-        uint32_t v = (uint32_t)t;
-        carry = t >> 32;
-        if (k == a.num_digits - 1 && top)
-            v &= (1u << top) - 1u;
-        if (k >= first)
-            a.value[k] = v;
+#ifndef PA_CARRY_PER_LARGE
+#define PA_CARRY_PER_LARGE 16
+#endif
+
+int carry_digits_per_thread(uint32_t num_digits)
+{
+    return num_digits >= (1u << 18) ? PA_CARRY_PER_LARGE : 4;
+}
+
+template <bool kApply>
+void launch_chunks(const CarryArgs& a, hipStream_t stream)
+{
+    switch (carry_digits_per_thread(a.num_digits)) {
+    case 16:
+        hipLaunchKernelGGL((k_carry<16, kApply>), dim3(a.chunks), dim3(kCarryThreads), 0, stream, a);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_carry<8, kApply>), dim3(a.chunks), dim3(kCarryThreads), 0, stream, a);
+        break;
+    default:
+        hipLaunchKernelGGL((k_carry<4, kApply>), dim3(a.chunks), dim3(kCarryThreads), 0, stream, a);
+        break;
     }
 }
 
-// Output word j = bits [n - m + 64 j, n - m + 64 j + 64) of V, masked to m bits.
-__global__ __launch_bounds__(256) void k_extract(CarryArgs a)
+hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream)
 {
-    const uint64_t words = (a.m + 63) >> 6;
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= words)
-        return;
-    const uint64_t bit = (a.n - a.m) + 64 * j;
-    const uint32_t q = (uint32_t)(bit >> 5);
-    const uint32_t sh = (uint32_t)(bit & 31);
-    const uint32_t D = a.num_digits;
-    const uint64_t v0 = q < D ? a.value[q] : 0;
-    const uint64_t v1 = q + 1 < D ? a.value[q + 1] : 0;
-    const uint64_t v2 = q + 2 < D ? a.value[q + 2] : 0;
-    uint64_t w = (v0 | (v1 << 32)) >> sh;
-    if (sh)
-        w |= v2 << (64 - sh);
-    if (j == words - 1 && (a.m & 63))
-        w &= (1ull << (a.m & 63)) - 1ull;
-    a.out[j] = w;
-}
-
-}  // namespace
-
-hipError_t launch_carry_chunk(const CarryArgs& a, hipStream_t stream)
-{
-    hipLaunchKernelGGL(k_carry_chunk, dim3(a.chunks), dim3(kCarryThreads), 0, stream, a);
+    launch_chunks<false>(a, stream);
     return hipGetLastError();
 }
 
@@ -240,14 +292,7 @@ hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream)
 
 hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_carry_apply, dim3(a.chunks), dim3(kCarryThreads), 0, stream, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_extract(const CarryArgs& a, hipStream_t stream)
-{
-    const uint64_t words = (a.m + 63) >> 6;
-    hipLaunchKernelGGL(k_extract, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream, a);
+    launch_chunks<true>(a, stream);
     return hipGetLastError();
 }
 

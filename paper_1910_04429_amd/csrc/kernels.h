@@ -10,7 +10,8 @@ namespace pa {
 
 constexpr int kTileLog = 14;                 // one LDS tile: 2^14 residues, 64 KB
 constexpr int kTile = 1 << kTileLog;
-constexpr int kStridedMaxLog = 9;            // strided passes: <= 512 rows x >= 32 columns
+constexpr int kTileMinLog = 10;              // smallest tile of a multi-pass transform
+constexpr int kStridedMaxLog = 9;            // strided passes: <= 512 rows
 constexpr int kMaxSteps = 4;
 constexpr int kPassThreads = 256;
 
@@ -57,10 +58,8 @@ struct PassArgs {
     Tables tb;
 };
 
-// Carry propagation, addend and bit extraction over the CRT-combined product.
+// CRT, carry propagation, addend and bit extraction over the product.
 constexpr int kCarryThreads = 256;
-constexpr int kCarryPerThread = 16;
-constexpr int kCarryChunk = kCarryThreads * kCarryPerThread;   // digits per chunk
 
 struct CarryArgs {
     const uint32_t* res;       // [kNumPrimes][L] residues of the product (natural order)
@@ -70,17 +69,19 @@ struct CarryArgs {
     int addend_src;            // kSrcDigits or kSrcSeed (no forced odd bit)
     const uint32_t* addend;    // kSrcDigits
     uint64_t seed;             // kSrcSeed
-    uint8_t* desc;             // [chunks] carry-transfer function of each chunk
-    uint8_t* carry_in;         // [chunks]
-    uint32_t* value;           // [D] digits of V (only the top m bits' digits written)
+    uint32_t* desc;            // [chunks] carry function of each chunk
+    uint32_t* carry_in;        // [chunks] carry entering each chunk
     uint64_t* out;             // ceil(m / 64) words
     uint32_t chunks;
 };
 
+// Digits per thread of the carry kernel for a block of D digits.
+int carry_digits_per_thread(uint32_t num_digits);
+
 hipError_t launch_pass(const PassArgs& a, hipStream_t stream);
-hipError_t launch_carry_chunk(const CarryArgs& a, hipStream_t stream);
+int pass_threads(int logN, int first_step);
+hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream);
 hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream);
 hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream);
-hipError_t launch_extract(const CarryArgs& a, hipStream_t stream);
 
 }  // namespace pa

@@ -155,7 +155,7 @@ __device__ void run_step(uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
     const uint32_t cmask = (1u << g.logC) - 1u;
     const uint32_t omask = (1u << g.logSig) - 1u;
     const bool twiddle = g.inner || g.colmul;
-    for (int q = threadIdx.x; q < ndft; q += kPassThreads) {
+    for (int q = threadIdx.x; q < ndft; q += blockDim.x) {
         const uint32_t c = (uint32_t)q & cmask;
         const uint32_t o = ((uint32_t)q >> g.logC) & omask;
         const uint32_t beta = (uint32_t)q >> (g.logC + g.logSig);
@@ -238,15 +238,15 @@ __device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int logC, int s, 
     g.inner = (s + 1 < a.nsteps);
     g.logM = a.r + a.s;
     g.col0 = col0;
-    // the pass factor omega_M^{j k}, k = k_0 + rho_0 k_1: step 0 takes
-    // omega_M^{j k_0}, step 1 (strided passes have at most two) omega_M^{j rho_0 k_1}
-    g.colmul = (a.s > 0) ? (s == 0 ? 1 : (1 << a.steps[0])) : 0;
+    // the pass factor omega_M^{j k} with k = k_0 + rho_0 (k_1 + rho_1 (k_2 + ...)):
+    // step s takes omega_M^{j rho_0 ... rho_{s-1} k_s}
+    g.colmul = (a.s > 0) ? (1 << above) : 0;
     return g;
 }
 
 __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
 {
-    __shared__ uint32_t sm[kTile];
+    extern __shared__ uint32_t sm[];          // 4 << logN bytes
 
     const int pi = blockIdx.y;
     const uint32_t p = kPrimes[pi], pneg = kNegInv[pi];
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
     // Tile element (row, c) <-> global position blk0 + row S + col0 + c; moved
     // in groups of 4 consecutive columns (C >= 4) or rows (C == 1).
     const int nq = N >> 2;
-    for (int u = threadIdx.x; u < nq; u += kPassThreads) {
+    for (int u = threadIdx.x; u < nq; u += blockDim.x) {
         uint32_t e, pos;
         if (logC >= 2) {
             const uint32_t row = (uint32_t)u >> (logC - 2);
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
             // Pointwise product with the pre-scaled c-hat (same layout), then
             // the inverse of this pass.
             const uint32_t* other = a.other + ((size_t)pi << a.logL);
-            for (int u = threadIdx.x; u < nq; u += kPassThreads) {
+            for (int u = threadIdx.x; u < nq; u += blockDim.x) {
                 const uint32_t e = (uint32_t)u << 2;
                 const uint4 cv = *reinterpret_cast<const uint4*>(other + blk0 + e);
                 uint4 v = *reinterpret_cast<uint4*>(&sm[swz(e)]);
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
         }
     }
 
-    for (int u = threadIdx.x; u < nq; u += kPassThreads) {
+    for (int u = threadIdx.x; u < nq; u += blockDim.x) {
         uint32_t e, pos;
         if (logC >= 2) {
             const uint32_t row = (uint32_t)u >> (logC - 2);
@@ -350,10 +350,19 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
 
 }  // namespace
 
+int pass_threads(int logN, int first_step)
+{
+    // one DFT of the first step per thread, between 1 and 4 waves
+    const int t = 1 << (logN - first_step);
+    return t < 64 ? 64 : (t > kPassThreads ? kPassThreads : t);
+}
+
 hipError_t launch_pass(const PassArgs& a, hipStream_t stream)
 {
     const unsigned tiles = 1u << (a.logL - a.logN);
-    hipLaunchKernelGGL(k_pass, dim3(tiles, kNumPrimes), dim3(kPassThreads), 0, stream, a);
+    const size_t lds = sizeof(uint32_t) << a.logN;
+    hipLaunchKernelGGL(k_pass, dim3(tiles, kNumPrimes), dim3(pass_threads(a.logN, a.steps[0])),
+                       lds, stream, a);
     return hipGetLastError();
 }
 

@@ -20,9 +20,7 @@ struct pa_ctx {
     uint64_t cap_L = 0, cap_D = 0;
     uint32_t* A = nullptr;            // c-hat   [3][L]
     uint32_t* B = nullptr;            // x-hat, then the product residues [3][L]
-    uint32_t* value = nullptr;        // [D] digits of V
-    uint8_t* desc = nullptr;          // [chunks]
-    uint8_t* carry_in = nullptr;      // [chunks]
+    uint32_t* status = nullptr;       // carry state: [chunks] functions, [chunks] carries
     // staging for the synchronous (host memory) entry points
     uint64_t cap_words = 0;
     uint64_t* d_key = nullptr;
@@ -105,31 +103,59 @@ int log2_len(uint64_t n)
     return l;
 }
 
-uint32_t chunks_of(uint64_t D) { return (uint32_t)((D + kCarryChunk - 1) / kCarryChunk); }
-
-// Passes of a length-2^l transform: strided passes of at most 2^9 rows, then
-// one contiguous pass of up to 2^14 points (a whole LDS tile).
-int plan_passes(int l, int* r)
+uint32_t chunks_of(uint64_t D)
 {
-    if (l <= kTileLog) {
+    const uint64_t chunk = (uint64_t)kCarryThreads * carry_digits_per_thread((uint32_t)D);
+    return (uint32_t)((D + chunk - 1) / chunk);
+}
+
+// Carry state words for the largest chunk count of any block up to D digits.
+uint64_t status_words(uint64_t D) { return 2 * ((D + kCarryThreads * 4 - 1) / (kCarryThreads * 4)); }
+
+// Tile size (log2 residues) for a length-2^l transform: whole 2^14 tiles for
+// long transforms, smaller ones for short transforms so that there are at
+// least 32 tiles per prime to spread over the chip.
+#ifndef PA_TILE_SLACK
+#define PA_TILE_SLACK 6
+#endif
+
+int plan_tile(int l)
+{
+    if (l <= kTileMinLog) return l;
+    int t = l - PA_TILE_SLACK;
+    if (t < kTileMinLog) t = kTileMinLog;
+    if (t > kTileLog) t = kTileLog;
+    return t;
+}
+
+// Passes of a length-2^l transform with tiles of 2^t: strided passes of at
+// most 2^9 rows (and at least 4 columns per tile), then one contiguous pass
+// over whole tiles.
+int plan_passes(int l, int t, int* r)
+{
+    if (l <= t) {
         r[0] = l;
         return 1;
     }
-    const int head = l - kTileLog;
-    const int k = (head + kStridedMaxLog - 1) / kStridedMaxLog;
+    const int head = l - t;
+    const int maxr = (t - 2 < kStridedMaxLog) ? t - 2 : kStridedMaxLog;
+    const int k = (head + maxr - 1) / maxr;
     for (int i = 0; i < k; ++i)
         r[i] = head / k + (i < head % k ? 1 : 0);
-    r[k] = kTileLog;
+    r[k] = t;
     return k + 1;
 }
 
-// Register steps of a length-2^r in-tile transform: radix 64 first, then the rest.
-int plan_steps(int r, int* st)
+// Register steps of a length-2^r in-tile transform in a tile of 2^t residues:
+// radix up to 64 in big tiles; smaller radices (more, shorter DFTs per step)
+// in small tiles, which have too few threads to hide the latency of long ones.
+int plan_steps(int r, int t, int* st)
 {
+    const int rmax = t >= 13 ? 6 : (t == 12 ? 5 : 4);
     int k = 0;
-    while (r > 6) {
-        st[k++] = 6;
-        r -= 6;
+    while (r > rmax) {
+        st[k++] = rmax;
+        r -= rmax;
     }
     st[k++] = r;
     return k;
@@ -139,11 +165,8 @@ void free_workspace(pa_ctx* ctx)
 {
     (void)hipFree(ctx->A);
     (void)hipFree(ctx->B);
-    (void)hipFree(ctx->value);
-    (void)hipFree(ctx->desc);
-    (void)hipFree(ctx->carry_in);
-    ctx->A = ctx->B = ctx->value = nullptr;
-    ctx->desc = ctx->carry_in = nullptr;
+    (void)hipFree(ctx->status);
+    ctx->A = ctx->B = ctx->status = nullptr;
     ctx->cap_L = ctx->cap_D = 0;
 }
 
@@ -155,13 +178,10 @@ int ensure_workspace(pa_ctx* ctx, uint64_t n)
         return PA_OK;
     PA_HIP(ctx, hipDeviceSynchronize());
     free_workspace(ctx);
-    const uint64_t ch = chunks_of(D);
     hipError_t e = hipSuccess;
     if ((e = hipMalloc(&ctx->A, kNumPrimes * L * sizeof(uint32_t))) != hipSuccess ||
         (e = hipMalloc(&ctx->B, kNumPrimes * L * sizeof(uint32_t))) != hipSuccess ||
-        (e = hipMalloc(&ctx->value, D * sizeof(uint32_t))) != hipSuccess ||
-        (e = hipMalloc(&ctx->desc, ch)) != hipSuccess ||
-        (e = hipMalloc(&ctx->carry_in, ch)) != hipSuccess) {
+        (e = hipMalloc(&ctx->status, status_words(D) * sizeof(uint32_t))) != hipSuccess) {
         free_workspace(ctx);
         return fail(ctx, PA_ENOMEM, "workspace allocation", e);
     }
@@ -239,9 +259,10 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     const uint64_t L = 1ull << l;
     const uint32_t D = (uint32_t)digits_of(n);
     int r[8];
-    const int P = plan_passes(l, r);
-    for (int i = 0; i + 1 < P; ++i)   // strided tiles need >= 32 columns
-        if (kTileLog - r[i] < 5) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    const int tlog = plan_tile(l);
+    const int P = plan_passes(l, tlog, r);
+    for (int i = 0; i + 1 < P; ++i)   // strided tiles need >= 4 columns
+        if (tlog - r[i] < 2) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     int s[8];
     {
         int rem = l;
@@ -258,14 +279,14 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     base.num_digits = D;
     base.n = n;
     base.logL = l;
-    base.logN = l < kTileLog ? l : kTileLog;
+    base.logN = tlog;
     base.tb = tb;
     base.rtw = ctx->rtw;
     base.store_limit = (uint32_t)L;
     auto geometry = [&](PassArgs& a, int i) {
         a.r = r[i];
         a.s = s[i];
-        a.nsteps = plan_steps(r[i], a.steps);
+        a.nsteps = plan_steps(r[i], tlog, a.steps);
     };
     const uint32_t limit = (uint32_t)((D + 3) & ~3ull);   // product digits kept
 
@@ -339,18 +360,14 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
         ca.addend_src = kSrcSeed;
         ca.seed = seed_b;
     }
-    ca.desc = ctx->desc;
-    ca.carry_in = ctx->carry_in;
-    ca.value = ctx->value;
-    ca.out = d_out;
     ca.chunks = chunks_of(D);
-    const uint64_t top_digits = D - ((n - m) >> 5);
-    const uint64_t out_bytes = words_of(m) * 8;
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_CHUNK, outD + ca.chunks, launch_carry_chunk(ca, stream));
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_SCAN, 2ull * ca.chunks, launch_carry_scan(ca, stream));
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, outD + ca.chunks + 4 * top_digits,
+    ca.desc = ctx->status;
+    ca.carry_in = ctx->status + ca.chunks;
+    ca.out = d_out;
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + 4ull * ca.chunks, launch_carry_local(ca, stream));
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_SCAN, 8ull * ca.chunks, launch_carry_scan(ca, stream));
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, outD + 4ull * ca.chunks + words_of(m) * 8,
               launch_carry_apply(ca, stream));
-    PA_LAUNCH(ctx, rec, PA_K_EXTRACT, 4 * top_digits + out_bytes, launch_extract(ca, stream));
     return PA_OK;
 }
 
@@ -383,7 +400,7 @@ uint64_t pa_workspace_bytes(uint64_t n)
     if (n == 0 || n > PA_MAX_N) return 0;
     const uint64_t L = 1ull << log2_len(n);
     const uint64_t D = digits_of(n);
-    return 2 * kNumPrimes * L * 4 + D * 4 + 2 * chunks_of(D);
+    return 2 * kNumPrimes * L * 4 + status_words(D) * 4;
 }
 
 int pa_init(pa_ctx** out, int device)
