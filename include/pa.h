@@ -122,6 +122,58 @@ typedef struct pa_profile {
 int pa_hash_profile(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_t seed_b,
                     uint64_t n, uint64_t m, uint64_t *d_out, void *stream, pa_profile *prof);
 
+/*
+ * Batches: many blocks of uneven n in one sequence of launches.  Blocks are
+ * grouped by transform length; every kernel of a group runs once for all of
+ * the group's blocks.  All pointers in a pa_job are device memory.
+ *   key:  ceil(n/64) words;  out: ceil(m/64) words
+ *   c, d: explicit operands (ceil(n/64) words each) or NULL to expand them
+ *         from seed_a / seed_b; an explicit c must be odd (eq. (6))
+ *   status: written by pa_batch_create / pa_hash_many: PA_OK, or the reason
+ *         the block was left out (its output is then untouched)
+ */
+typedef struct pa_job {
+    const uint64_t *key;
+    const uint64_t *c;
+    const uint64_t *d;
+    uint64_t seed_a, seed_b;
+    uint64_t n, m;
+    uint64_t *out;
+    int status;
+} pa_job;
+
+typedef struct pa_batch pa_batch;
+
+/*
+ * Validate and plan a batch, allocate its device workspace (one slab for all
+ * blocks; see pa_batch_bytes) and upload its job table.  Invalid blocks get
+ * their status and are skipped; the call fails only if nothing can run (or on
+ * allocation / device errors).  The batch keeps the pointers of `jobs`, not
+ * the array itself; the buffers they point to must outlive the batch.
+ */
+int pa_batch_create(pa_ctx *ctx, pa_job *jobs, size_t count, pa_batch **batch);
+
+/* Queue every kernel of the batch on `stream` (replays the captured graph if
+ * pa_batch_capture was called).  Returns without waiting. */
+int pa_batch_run(pa_batch *batch, void *stream);
+
+/* Record the batch's launches into a HIP graph on `stream` (NULL: the
+ * context's stream) so that later pa_batch_run calls replay it with one
+ * launch.  Nothing runs during the capture. */
+int pa_batch_capture(pa_batch *batch, void *stream);
+
+/* Device bytes the batch holds (workspace + job table). */
+uint64_t pa_batch_bytes(const pa_batch *batch);
+
+/* Number of blocks that will run, and of launches one run queues. */
+size_t pa_batch_size(const pa_batch *batch);
+size_t pa_batch_launches(const pa_batch *batch);
+
+void pa_batch_destroy(pa_batch *batch);
+
+/* create + run + wait + destroy; per-block status in jobs[i].status. */
+int pa_hash_many(pa_ctx *ctx, pa_job *jobs, size_t count, void *stream);
+
 /* Size the workspace for blocks of up to n_max bits now. */
 int pa_reserve(pa_ctx *ctx, uint64_t n_max);
 

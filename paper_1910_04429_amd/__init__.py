@@ -47,6 +47,13 @@ class _Profile(ctypes.Structure):
                 ("bytes", ctypes.c_uint64 * PA_PROFILE_MAX)]
 
 
+class _Job(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("c", ctypes.c_void_p), ("d", ctypes.c_void_p),
+                ("seed_a", ctypes.c_uint64), ("seed_b", ctypes.c_uint64),
+                ("n", ctypes.c_uint64), ("m", ctypes.c_uint64),
+                ("out", ctypes.c_void_p), ("status", ctypes.c_int)]
+
+
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _u64 = ctypes.c_uint64
 
@@ -85,6 +92,24 @@ _lib.pa_workspace_bytes.restype = _u64
 _lib.pa_workspace_bytes.argtypes = [_u64]
 _lib.pa_transform_length.restype = _u64
 _lib.pa_transform_length.argtypes = [_u64]
+_lib.pa_batch_create.restype = ctypes.c_int
+_lib.pa_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Job), ctypes.c_size_t,
+                                 ctypes.POINTER(ctypes.c_void_p)]
+_lib.pa_batch_run.restype = ctypes.c_int
+_lib.pa_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+_lib.pa_batch_capture.restype = ctypes.c_int
+_lib.pa_batch_capture.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+_lib.pa_batch_bytes.restype = _u64
+_lib.pa_batch_bytes.argtypes = [ctypes.c_void_p]
+_lib.pa_batch_size.restype = ctypes.c_size_t
+_lib.pa_batch_size.argtypes = [ctypes.c_void_p]
+_lib.pa_batch_launches.restype = ctypes.c_size_t
+_lib.pa_batch_launches.argtypes = [ctypes.c_void_p]
+_lib.pa_batch_destroy.restype = None
+_lib.pa_batch_destroy.argtypes = [ctypes.c_void_p]
+_lib.pa_hash_many.restype = ctypes.c_int
+_lib.pa_hash_many.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Job), ctypes.c_size_t,
+                              ctypes.c_void_p]
 
 MASK64 = (1 << 64) - 1
 
@@ -188,6 +213,73 @@ def pa_workspace_bytes(n: int) -> int:
 
 def pa_transform_length(n: int) -> int:
     return int(_lib.pa_transform_length(n))
+
+
+def _job_array(jobs):
+    """jobs: dicts with key/out device tensors, n, m, seed_a, seed_b and
+    optional c/d device tensors."""
+    arr = (_Job * len(jobs))()
+    for i, j in enumerate(jobs):
+        n, m = int(j["n"]), int(j["m"])
+        arr[i].key = _dev_ptr(j["key"], words(n), "key")
+        arr[i].out = _dev_ptr(j["out"], words(m), "out")
+        arr[i].c = _dev_ptr(j["c"], words(n), "c") if j.get("c") is not None else None
+        arr[i].d = _dev_ptr(j["d"], words(n), "d") if j.get("d") is not None else None
+        arr[i].seed_a = int(j.get("seed_a", 0)) & MASK64
+        arr[i].seed_b = int(j.get("seed_b", 0)) & MASK64
+        arr[i].n, arr[i].m = n, m
+        arr[i].status = -1
+    return arr
+
+
+def pa_hash_many(ctx, jobs, stream=None) -> list[int]:
+    """Hash every block of `jobs` (see _job_array) and wait; per-block status."""
+    arr = _job_array(jobs)
+    _check(ctx, _lib.pa_hash_many(ctx, arr, len(jobs), _stream_handle(stream)))
+    return [arr[i].status for i in range(len(jobs))]
+
+
+class Batch:
+    """pa_batch: a planned batch whose launches can be replayed (and captured
+    into a HIP graph).  Keeps the job array alive with the batch."""
+
+    def __init__(self, ctx, jobs):
+        self.ctx = ctx
+        self._jobs = _job_array(jobs)
+        self._refs = jobs
+        h = ctypes.c_void_p()
+        _check(ctx, _lib.pa_batch_create(ctx, self._jobs, len(jobs), ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def status(self) -> list[int]:
+        return [self._jobs[i].status for i in range(len(self._jobs))]
+
+    def run(self, stream=None):
+        _check(self.ctx, _lib.pa_batch_run(self.h, _stream_handle(stream)))
+
+    def capture(self, stream=None):
+        _check(self.ctx, _lib.pa_batch_capture(self.h, _stream_handle(stream)))
+
+    def bytes(self) -> int:
+        return int(_lib.pa_batch_bytes(self.h))
+
+    def size(self) -> int:
+        return int(_lib.pa_batch_size(self.h))
+
+    def launches(self) -> int:
+        return int(_lib.pa_batch_launches(self.h))
+
+    def close(self):
+        if self.h:
+            _lib.pa_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:

@@ -106,9 +106,35 @@ __device__ __forceinline__ int slot(int i)
 
 // kApply = false: write the chunk's carry function.  kApply = true: resolve the
 // chunk with its carry-in and write its output words.
+// Batch mode: take the block's sizes, addend, state and output from its job.
+__device__ __forceinline__ void bind_job(CarryArgs& a, uint32_t job)
+{
+    const JobDesc& j = a.jobs[job];
+    a.res = j.B;
+    a.num_digits = j.num_digits;
+    a.n = j.n;
+    a.m = j.m;
+    if (j.d) {
+        a.addend_src = kSrcDigits;
+        a.addend = j.d;
+    } else {
+        a.addend_src = kSrcSeed;
+        a.seed = j.seed_b;
+    }
+    a.desc = j.carry;
+    a.carry_in = j.carry + j.chunks;
+    a.out = j.out;
+    a.chunks = j.chunks;
+}
+
 template <int kPer, bool kApply>
 __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
 {
+    if (a.jobs) {
+        bind_job(a, blockIdx.y);
+        if (blockIdx.x >= a.chunks)
+            return;
+    }
     constexpr int kChunk = kCarryThreads * kPer;
     constexpr int kSpan = kChunk + 4;                      // digits -2 .. kChunk+1
     constexpr int kSlots = kSpan + kSpan / kPer + 1;
@@ -229,6 +255,8 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
 __global__ __launch_bounds__(1024) void k_carry_scan(CarryArgs a)
 {
     __shared__ uint32_t sh[1024];
+    if (a.jobs)
+        bind_job(a, blockIdx.x);
     const int tid = threadIdx.x;
     const uint32_t per = (a.chunks + 1023) / 1024;
     const uint32_t j0 = tid * per;
@@ -263,36 +291,37 @@ int carry_digits_per_thread(uint32_t num_digits)
 }
 
 template <bool kApply>
-void launch_chunks(const CarryArgs& a, hipStream_t stream)
+void launch_chunks(const CarryArgs& a, hipStream_t stream, unsigned batch)
 {
-    switch (carry_digits_per_thread(a.num_digits)) {
+    const dim3 grid(a.chunks, batch);
+    switch (a.per) {
     case 16:
-        hipLaunchKernelGGL((k_carry<16, kApply>), dim3(a.chunks), dim3(kCarryThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_carry<16, kApply>), grid, dim3(kCarryThreads), 0, stream, a);
         break;
     case 8:
-        hipLaunchKernelGGL((k_carry<8, kApply>), dim3(a.chunks), dim3(kCarryThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_carry<8, kApply>), grid, dim3(kCarryThreads), 0, stream, a);
         break;
     default:
-        hipLaunchKernelGGL((k_carry<4, kApply>), dim3(a.chunks), dim3(kCarryThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_carry<4, kApply>), grid, dim3(kCarryThreads), 0, stream, a);
         break;
     }
 }
 
-hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream)
+hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned batch)
 {
-    launch_chunks<false>(a, stream);
+    launch_chunks<false>(a, stream, batch);
     return hipGetLastError();
 }
 
-hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream)
+hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch)
 {
-    hipLaunchKernelGGL(k_carry_scan, dim3(1), dim3(1024), 0, stream, a);
+    hipLaunchKernelGGL(k_carry_scan, dim3(batch), dim3(1024), 0, stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream)
+hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream, unsigned batch)
 {
-    launch_chunks<true>(a, stream);
+    launch_chunks<true>(a, stream, batch);
     return hipGetLastError();
 }
 

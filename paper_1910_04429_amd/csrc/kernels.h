@@ -29,6 +29,29 @@ enum Source : int {
     kSrcSeed = 2,    // digits of the SplitMix64 stream of `seed`, bit 0 forced to 1
 };
 
+// One block of a batch: where its operands, spectra, carry state and output
+// live.  Kernels launched for a batch take the block from blockIdx.z (passes)
+// or blockIdx.y (carry) and read these fields instead of the scalar ones.
+struct JobDesc {
+    const uint32_t* key;       // key digits (32-bit view of the key words)
+    const uint32_t* c;         // explicit multiplier digits, or null: seeded
+    const uint32_t* d;         // explicit addend digits, or null: seeded
+    uint64_t seed_a, seed_b;
+    uint64_t n, m;
+    uint32_t num_digits;       // ceil(n / 32)
+    uint32_t chunks;           // carry chunks
+    uint32_t* A;               // c-hat [kNumPrimes][L]
+    uint32_t* B;               // x-hat, then the product [kNumPrimes][L]
+    uint32_t* carry;           // [2 * chunks]: chunk functions, then carries in
+    uint64_t* out;             // ceil(m / 64) words
+};
+
+enum Role : int {
+    kRoleMul = 0,    // transform of the multiplier c into A
+    kRoleKey = 1,    // transform of the key x into B (last pass fused)
+    kRoleInv = 2,    // inverse passes on B
+};
+
 enum PassMode : int {
     kForward = 0,    // load, DIF, post-twiddle, store (last pass: keep bit-reversed)
     kInverse = 1,    // load, pre-twiddle, DIT, store natural order
@@ -56,6 +79,10 @@ struct PassArgs {
     int scale;                 // multiply the stored output by scale_w (Shoup)
     uint32_t scale_w[kNumPrimes], scale_q[kNumPrimes];
     Tables tb;
+    // batch mode (jobs != null): per-block fields come from jobs[blockIdx.z]
+    const JobDesc* jobs;
+    int role;
+    int limit_to_digits;       // store only positions < ceil(D / 4) * 4
 };
 
 // CRT, carry propagation, addend and bit extraction over the product.
@@ -72,16 +99,18 @@ struct CarryArgs {
     uint32_t* desc;            // [chunks] carry function of each chunk
     uint32_t* carry_in;        // [chunks] carry entering each chunk
     uint64_t* out;             // ceil(m / 64) words
-    uint32_t chunks;
+    uint32_t chunks;           // grid width (the largest chunk count in a batch)
+    int per;                   // digits per thread (4, 8 or 16)
+    const JobDesc* jobs;       // batch mode: per-block fields from jobs[blockIdx.y]
 };
 
 // Digits per thread of the carry kernel for a block of D digits.
 int carry_digits_per_thread(uint32_t num_digits);
 
-hipError_t launch_pass(const PassArgs& a, hipStream_t stream);
+hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch = 1);
 int pass_threads(int logN, int first_step);
-hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream);
-hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream);
-hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream);
+hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
+hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
+hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
 
 }  // namespace pa

@@ -244,9 +244,35 @@ __device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int logC, int s, 
     return g;
 }
 
+// Batch mode: take the block's pointers, sizes and sources from its job.
+__device__ __forceinline__ void bind_job(PassArgs& a)
+{
+    const JobDesc& j = a.jobs[blockIdx.z];
+    a.n = j.n;
+    a.num_digits = j.num_digits;
+    a.data = (a.role == kRoleMul) ? j.A : j.B;
+    a.other = j.A;
+    if (a.src != kSrcArray) {                 // first pass: the operand's digits
+        if (a.role == kRoleKey) {
+            a.src = kSrcDigits;
+            a.digits = j.key;
+        } else if (j.c) {
+            a.src = kSrcDigits;
+            a.digits = j.c;
+        } else {
+            a.src = kSrcSeed;
+            a.seed = j.seed_a;
+        }
+    }
+    if (a.limit_to_digits)
+        a.store_limit = (j.num_digits + 3u) & ~3u;
+}
+
 __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
 {
     extern __shared__ uint32_t sm[];          // 4 << logN bytes
+    if (a.jobs)
+        bind_job(a);
 
     const int pi = blockIdx.y;
     const uint32_t p = kPrimes[pi], pneg = kNegInv[pi];
@@ -357,12 +383,12 @@ int pass_threads(int logN, int first_step)
     return t < 64 ? 64 : (t > kPassThreads ? kPassThreads : t);
 }
 
-hipError_t launch_pass(const PassArgs& a, hipStream_t stream)
+hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch)
 {
     const unsigned tiles = 1u << (a.logL - a.logN);
     const size_t lds = sizeof(uint32_t) << a.logN;
-    hipLaunchKernelGGL(k_pass, dim3(tiles, kNumPrimes), dim3(pass_threads(a.logN, a.steps[0])),
-                       lds, stream, a);
+    hipLaunchKernelGGL(k_pass, dim3(tiles, kNumPrimes, batch),
+                       dim3(pass_threads(a.logN, a.steps[0])), lds, stream, a);
     return hipGetLastError();
 }
 

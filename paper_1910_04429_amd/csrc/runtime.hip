@@ -2,7 +2,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "../../include/pa.h"
 #include "kernels.h"
@@ -27,6 +29,11 @@ struct pa_ctx {
     uint64_t* d_c = nullptr;
     uint64_t* d_d = nullptr;
     uint64_t* d_out = nullptr;
+    // side streams (default priority) on which batch groups run concurrently
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSide] = {};
     hipEvent_t ev[2 * PA_PROFILE_MAX] = {};
     bool have_events = false;
     char err[512] = {0};
@@ -112,17 +119,18 @@ uint32_t chunks_of(uint64_t D)
 // Carry state words for the largest chunk count of any block up to D digits.
 uint64_t status_words(uint64_t D) { return 2 * ((D + kCarryThreads * 4 - 1) / (kCarryThreads * 4)); }
 
-// Tile size (log2 residues) for a length-2^l transform: whole 2^14 tiles for
-// long transforms, smaller ones for short transforms so that there are at
-// least 32 tiles per prime to spread over the chip.
 #ifndef PA_TILE_SLACK
 #define PA_TILE_SLACK 6
 #endif
 
-int plan_tile(int l)
+// Tile size (log2 residues) for a length-2^l transform run for `blocks`
+// blocks at once: whole 2^14 tiles when there is parallelism to spare (a
+// batch, or a long transform); for a lone short transform, smaller tiles so
+// that there are enough workgroups to spread over the chip.
+int plan_tile(int l, unsigned blocks = 1)
 {
     if (l <= kTileMinLog) return l;
-    int t = l - PA_TILE_SLACK;
+    int t = blocks >= 16 ? l : l - PA_TILE_SLACK;
     if (t < kTileMinLog) t = kTileMinLog;
     if (t > kTileLog) t = kTileLog;
     return t;
@@ -247,127 +255,260 @@ struct Recorder {
         if (rec) PA_HIP(ctx, (rec)->end());                                      \
     } while (0)
 
-// Queue the whole hash on `stream`.  c_digits / d_digits select explicit
-// operands (device, 32-bit digit view); null means expand from the seeds.
+// Transform plan for L = 2^l: tile size, passes, register steps, output scale.
+struct Plan {
+    int l = 0, t = 0, P = 0;
+    int r[8] = {}, s[8] = {};
+    int nsteps[8] = {};
+    int steps[8][kMaxSteps] = {};
+    uint32_t scale_w[kNumPrimes] = {}, scale_q[kNumPrimes] = {};
+};
+
+bool make_plan(int l, Plan* pl, unsigned blocks = 1)
+{
+    pl->l = l;
+    pl->t = plan_tile(l, blocks);
+    pl->P = plan_passes(l, pl->t, pl->r);
+    int rem = l;
+    for (int i = 0; i < pl->P; ++i) {
+        if (i + 1 < pl->P && pl->t - pl->r[i] < 2) return false;   // strided tiles: >= 4 columns
+        rem -= pl->r[i];
+        pl->s[i] = rem;
+        pl->nsteps[i] = plan_steps(pl->r[i], pl->t, pl->steps[i]);
+    }
+    // c-hat is scaled on its last pass by 2^32 / L so that the Montgomery
+    // pointwise product yields x-hat c-hat / L.
+    const uint64_t L = 1ull << l;
+    for (int pi = 0; pi < kNumPrimes; ++pi) {
+        const uint64_t p = kPrimes[pi];
+        const uint64_t w = ((1ull << 32) % p) * hpow(L % p, p - 2, p) % p;
+        pl->scale_w[pi] = (uint32_t)w;
+        pl->scale_q[pi] = hshoup(w, p);
+    }
+    return true;
+}
+
+// Operands of one block.  In batch mode the kernels read them from the job
+// table instead, and `key_bytes` / `digits` / `out_bytes` are batch totals
+// used only for the profile's byte counts.
+struct Work {
+    const uint32_t* key = nullptr;     // key digits
+    const uint32_t* c = nullptr;       // explicit c digits or null
+    const uint32_t* d = nullptr;       // explicit d digits or null
+    uint64_t seed_a = 0, seed_b = 0, n = 0, m = 0;
+    uint32_t* A = nullptr;
+    uint32_t* B = nullptr;
+    uint32_t* carry = nullptr;
+    uint64_t* out = nullptr;
+    // batch mode
+    const JobDesc* jobs = nullptr;
+    unsigned batch = 1;
+    uint32_t chunks = 0;               // grid width of the carry kernels
+    int per = 4;                       // carry digits per thread
+    uint64_t key_bytes = 0, digits = 0, out_bytes = 0;
+};
+
+// Queue every kernel of the hash (or of one batch group) on `stream`.
+int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
+                 Recorder* rec = nullptr)
+{
+    const unsigned batch = w.batch;
+    const uint64_t L = 1ull << pl.l;
+    const uint64_t arr = batch * kNumPrimes * 4ull * L;    // residue arrays, all blocks
+    const uint64_t outD = kNumPrimes * 4ull * w.digits;    // product coefficients kept
+    const int P = pl.P;
+
+    PassArgs base{};
+    base.num_digits = (uint32_t)digits_of(w.n);
+    base.n = w.n;
+    base.logL = pl.l;
+    base.logN = pl.t;
+    base.tb = Tables{ctx->pass_lo, ctx->pass_hi};
+    base.rtw = ctx->rtw;
+    base.store_limit = (uint32_t)L;
+    base.jobs = w.jobs;
+    auto geometry = [&](PassArgs& a, int i) {
+        a.r = pl.r[i];
+        a.s = pl.s[i];
+        a.nsteps = pl.nsteps[i];
+        for (int k = 0; k < kMaxSteps; ++k) a.steps[k] = pl.steps[i][k];
+    };
+    const uint32_t limit = (uint32_t)((digits_of(w.n) + 3) & ~3ull);
+
+    for (int i = 0; i < P; ++i) {                           // c-hat
+        PassArgs a = base;
+        a.role = kRoleMul;
+        a.data = w.A;
+        geometry(a, i);
+        a.mode = kForward;
+        a.src = kSrcArray;
+        if (i == 0) {
+            if (w.c) {
+                a.src = kSrcDigits;
+                a.digits = w.c;
+            } else {
+                a.src = kSrcSeed;
+                a.seed = w.seed_a;
+            }
+        }
+        if (i == P - 1) {
+            a.scale = 1;
+            for (int pi = 0; pi < kNumPrimes; ++pi) {
+                a.scale_w[pi] = pl.scale_w[pi];
+                a.scale_q[pi] = pl.scale_q[pi];
+            }
+        }
+        const uint64_t in = (i == 0) ? (w.c ? w.key_bytes : 0) : arr;
+        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + arr, launch_pass(a, stream, batch));
+    }
+    for (int i = 0; i < P; ++i) {                           // x-hat, pointwise, last inverse pass
+        PassArgs a = base;
+        a.role = kRoleKey;
+        a.data = w.B;
+        geometry(a, i);
+        a.mode = (i == P - 1) ? kFused : kForward;
+        if (P == 1) {
+            a.store_limit = limit;
+            a.limit_to_digits = 1;
+        }
+        a.other = w.A;
+        a.src = (i == 0) ? kSrcDigits : kSrcArray;
+        a.digits = w.key;
+        uint64_t in = (i == 0) ? w.key_bytes : arr, outb = arr;
+        if (i == P - 1) {
+            in += arr;
+            if (P == 1) outb = outD;
+        }
+        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + outb, launch_pass(a, stream, batch));
+    }
+    for (int i = P - 2; i >= 0; --i) {                      // remaining inverse passes
+        PassArgs a = base;
+        a.role = kRoleInv;
+        a.data = w.B;
+        geometry(a, i);
+        a.mode = kInverse;
+        a.src = kSrcArray;
+        if (i == 0) {
+            a.store_limit = limit;
+            a.limit_to_digits = 1;
+        }
+        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, arr + (i == 0 ? outD : arr),
+                  launch_pass(a, stream, batch));
+    }
+    CarryArgs ca{};
+    ca.res = w.B;
+    ca.L = (uint32_t)L;
+    ca.num_digits = (uint32_t)digits_of(w.n);
+    ca.n = w.n;
+    ca.m = w.m;
+    if (w.d) {
+        ca.addend_src = kSrcDigits;
+        ca.addend = w.d;
+    } else {
+        ca.addend_src = kSrcSeed;
+        ca.seed = w.seed_b;
+    }
+    ca.chunks = w.chunks;
+    ca.per = w.per;
+    ca.desc = w.carry;
+    ca.carry_in = w.carry ? w.carry + w.chunks : nullptr;
+    ca.out = w.out;
+    ca.jobs = w.jobs;
+    const uint64_t chunk_bytes = 4ull * w.chunks * batch;
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + chunk_bytes, launch_carry_local(ca, stream, batch));
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_SCAN, 2 * chunk_bytes, launch_carry_scan(ca, stream, batch));
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, outD + chunk_bytes + w.out_bytes,
+              launch_carry_apply(ca, stream, batch));
+    return PA_OK;
+}
+
+// Queue the hash of one block held in the context's workspace.  c_words /
+// d_words select explicit operands (device memory); null means seeded.
 int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const uint64_t* d_words,
             uint64_t seed_a, uint64_t seed_b, uint64_t n, uint64_t m, uint64_t* d_out,
             hipStream_t stream, Recorder* rec = nullptr)
 {
     int rc = ensure_workspace(ctx, n);
     if (rc) return rc;
-    const int l = log2_len(n);
-    const uint64_t L = 1ull << l;
-    const uint32_t D = (uint32_t)digits_of(n);
-    int r[8];
-    const int tlog = plan_tile(l);
-    const int P = plan_passes(l, tlog, r);
-    for (int i = 0; i + 1 < P; ++i)   // strided tiles need >= 4 columns
-        if (tlog - r[i] < 2) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
-    int s[8];
-    {
-        int rem = l;
-        for (int i = 0; i < P; ++i) {
-            rem -= r[i];
-            s[i] = rem;
-        }
-    }
-    Tables tb{ctx->pass_lo, ctx->pass_hi};
-    const uint64_t arr = kNumPrimes * 4ull * L;        // one residue array
-    const uint64_t outD = kNumPrimes * 4ull * D;       // the product coefficients kept
+    Plan pl;
+    if (!make_plan(log2_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    Work w;
+    w.key = reinterpret_cast<const uint32_t*>(d_key);
+    w.c = reinterpret_cast<const uint32_t*>(c_words);
+    w.d = reinterpret_cast<const uint32_t*>(d_words);
+    w.seed_a = seed_a;
+    w.seed_b = seed_b;
+    w.n = n;
+    w.m = m;
+    w.A = ctx->A;
+    w.B = ctx->B;
+    w.carry = ctx->status;
+    w.out = d_out;
+    w.chunks = chunks_of(digits_of(n));
+    w.per = carry_digits_per_thread((uint32_t)digits_of(n));
+    w.key_bytes = (n + 7) / 8;
+    w.digits = digits_of(n);
+    w.out_bytes = words_of(m) * 8;
+    return enqueue_plan(ctx, pl, w, stream, rec);
+}
 
-    PassArgs base{};
-    base.num_digits = D;
-    base.n = n;
-    base.logL = l;
-    base.logN = tlog;
-    base.tb = tb;
-    base.rtw = ctx->rtw;
-    base.store_limit = (uint32_t)L;
-    auto geometry = [&](PassArgs& a, int i) {
-        a.r = r[i];
-        a.s = s[i];
-        a.nsteps = plan_steps(r[i], tlog, a.steps);
+}  // namespace
+
+struct pa_batch {
+    pa_ctx* ctx = nullptr;
+    struct Group {
+        Plan plan;
+        uint32_t first = 0, count = 0;   // range in the job table
+        uint32_t chunks = 0;             // widest carry grid of the group
+        int per = 4;
+        uint64_t key_bytes = 0, digits = 0, out_bytes = 0;
     };
-    const uint32_t limit = (uint32_t)((D + 3) & ~3ull);   // product digits kept
+    std::vector<Group> groups;
+    JobDesc* d_jobs = nullptr;
+    uint8_t* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    size_t valid = 0;
+    size_t launches = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
-    // c-hat, scaled on its last pass by 2^32 / L so that the Montgomery
-    // pointwise product yields x-hat c-hat / L.
-    for (int i = 0; i < P; ++i) {
-        PassArgs a = base;
-        a.data = ctx->A;
-        geometry(a, i);
-        a.mode = kForward;
-        a.src = kSrcArray;
-        if (i == 0) {
-            if (c_words) {
-                a.src = kSrcDigits;
-                a.digits = reinterpret_cast<const uint32_t*>(c_words);
-            } else {
-                a.src = kSrcSeed;
-                a.seed = seed_a;
-            }
+namespace {
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Groups are independent: they run concurrently on the context's side
+// streams, forked from and joined back into `stream` with events (this also
+// holds inside a graph capture, where it becomes parallel branches).
+int enqueue_batch(pa_batch* b, hipStream_t stream)
+{
+    pa_ctx* ctx = b->ctx;
+    const int ns = (int)std::min<size_t>(b->groups.size(), pa_ctx::kSide);
+    if (ns > 1) {
+        PA_HIP(ctx, hipEventRecord(ctx->fork, stream));
+        for (int i = 0; i < ns; ++i) PA_HIP(ctx, hipStreamWaitEvent(ctx->side[i], ctx->fork, 0));
+    }
+    // largest transforms first, so the long groups start early
+    for (size_t gi = b->groups.size(); gi-- > 0;) {
+        const auto& g = b->groups[gi];
+        const hipStream_t st = ns > 1 ? ctx->side[gi % ns] : stream;
+        Work w;
+        w.jobs = b->d_jobs + g.first;
+        w.batch = g.count;
+        w.chunks = g.chunks;
+        w.per = g.per;
+        w.key_bytes = g.key_bytes;
+        w.digits = g.digits;
+        w.out_bytes = g.out_bytes;
+        int rc = enqueue_plan(ctx, g.plan, w, st);
+        if (rc) return rc;
+    }
+    if (ns > 1) {
+        for (int i = 0; i < ns; ++i) {
+            PA_HIP(ctx, hipEventRecord(ctx->join[i], ctx->side[i]));
+            PA_HIP(ctx, hipStreamWaitEvent(stream, ctx->join[i], 0));
         }
-        if (i == P - 1) {
-            a.scale = 1;
-            for (int pi = 0; pi < kNumPrimes; ++pi) {
-                const uint64_t p = kPrimes[pi];
-                const uint64_t w = ((1ull << 32) % p) * hpow(L % p, p - 2, p) % p;
-                a.scale_w[pi] = (uint32_t)w;
-                a.scale_q[pi] = hshoup(w, p);
-            }
-        }
-        const uint64_t in = (i == 0) ? (c_words ? (n + 7) / 8 : 0) : arr;
-        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + arr, launch_pass(a, stream));
     }
-    // x-hat, pointwise, and the inverse of the last pass, fused.
-    for (int i = 0; i < P; ++i) {
-        PassArgs a = base;
-        a.data = ctx->B;
-        geometry(a, i);
-        a.mode = (i == P - 1) ? kFused : kForward;
-        if (P == 1) a.store_limit = limit;
-        a.other = ctx->A;
-        a.src = (i == 0) ? kSrcDigits : kSrcArray;
-        a.digits = reinterpret_cast<const uint32_t*>(d_key);
-        uint64_t in = (i == 0) ? (n + 7) / 8 : arr, outb = arr;
-        if (i == P - 1) {
-            in += arr;                       // c-hat
-            if (P == 1) outb = outD;         // also the last inverse pass
-        }
-        const uint64_t bytes = in + outb;
-        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, bytes, launch_pass(a, stream));
-    }
-    // remaining inverse passes
-    for (int i = P - 2; i >= 0; --i) {
-        PassArgs a = base;
-        a.data = ctx->B;
-        geometry(a, i);
-        a.mode = kInverse;
-        a.src = kSrcArray;
-        if (i == 0) a.store_limit = limit;
-        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, arr + (i == 0 ? outD : arr), launch_pass(a, stream));
-    }
-    CarryArgs ca{};
-    ca.res = ctx->B;
-    ca.L = (uint32_t)L;
-    ca.num_digits = D;
-    ca.n = n;
-    ca.m = m;
-    if (d_words) {
-        ca.addend_src = kSrcDigits;
-        ca.addend = reinterpret_cast<const uint32_t*>(d_words);
-    } else {
-        ca.addend_src = kSrcSeed;
-        ca.seed = seed_b;
-    }
-    ca.chunks = chunks_of(D);
-    ca.desc = ctx->status;
-    ca.carry_in = ctx->status + ca.chunks;
-    ca.out = d_out;
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + 4ull * ca.chunks, launch_carry_local(ca, stream));
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_SCAN, 8ull * ca.chunks, launch_carry_scan(ca, stream));
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, outD + 4ull * ca.chunks + words_of(m) * 8,
-              launch_carry_apply(ca, stream));
     return PA_OK;
 }
 
@@ -423,6 +564,14 @@ int pa_init(pa_ctx** out, int device)
     do {
         if (hipSetDevice(device) != hipSuccess) { rc = PA_ENODEV; break; }
         if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            rc = PA_EDEVICE;
+            break;
+        }
+        bool ok = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; i < pa_ctx::kSide && ok; ++i)
+            ok = hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&ctx->join[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
             rc = PA_EDEVICE;
             break;
         }
@@ -495,6 +644,11 @@ void pa_destroy(pa_ctx* ctx)
     (void)hipFree(ctx->pass_hi);
     if (ctx->have_events)
         for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+    for (int i = 0; i < pa_ctx::kSide; ++i) {
+        if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+        if (ctx->join[i]) (void)hipEventDestroy(ctx->join[i]);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -584,6 +738,187 @@ int pa_hash_ex(pa_ctx* ctx, const uint64_t* key, const uint64_t* c, const uint64
 {
     if (!c || !d) return ctx ? fail(ctx, PA_EINVAL, "null operand") : PA_EINVAL;
     return hash_host(ctx, key, c, d, 0, 0, n, m, out);
+}
+
+void pa_batch_destroy(pa_batch* b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->ctx->device);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    (void)hipFree(b->d_jobs);
+    (void)hipFree(b->ws);
+    delete b;
+}
+
+int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
+{
+    if (!ctx || !out || (!jobs && count)) return PA_EINVAL;
+    *out = nullptr;
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    // validate
+    std::vector<size_t> ok;
+    for (size_t i = 0; i < count; ++i) {
+        pa_job& j = jobs[i];
+        j.status = PA_OK;
+        if (j.n == 0 || j.m == 0 || j.m > j.n || j.n > PA_MAX_N || !j.key || !j.out ||
+            (j.c && !j.d) || (!j.c && j.d)) {
+            j.status = PA_EINVAL;
+            continue;
+        }
+        if (j.c) {
+            uint64_t w0 = 0;
+            if (hipMemcpy(&w0, j.c, 8, hipMemcpyDeviceToHost) != hipSuccess) {
+                j.status = PA_EDEVICE;
+                continue;
+            }
+            if ((w0 & 1) == 0) {
+                j.status = PA_EINVAL;
+                continue;
+            }
+        }
+        ok.push_back(i);
+    }
+    if (ok.empty()) return fail(ctx, PA_EINVAL, "no valid block in the batch");
+    std::stable_sort(ok.begin(), ok.end(), [&](size_t a, size_t b) {
+        return log2_len(jobs[a].n) < log2_len(jobs[b].n);
+    });
+    pa_batch* b = new (std::nothrow) pa_batch;
+    if (!b) return PA_ENOMEM;
+    b->ctx = ctx;
+    b->valid = ok.size();
+    // groups and workspace layout
+    std::vector<JobDesc> h(ok.size());
+    std::vector<uint64_t> offA(ok.size()), offC(ok.size());
+    uint64_t bytes = 0;
+    for (size_t i = 0; i < ok.size();) {
+        const int l = log2_len(jobs[ok[i]].n);
+        size_t e = i;
+        uint64_t maxD = 0;
+        while (e < ok.size() && log2_len(jobs[ok[e]].n) == l) {
+            maxD = std::max<uint64_t>(maxD, digits_of(jobs[ok[e]].n));
+            ++e;
+        }
+        pa_batch::Group g;
+        if (!make_plan(l, &g.plan, (unsigned)(e - i))) {
+            delete b;
+            return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+        }
+        g.first = (uint32_t)i;
+        g.count = (uint32_t)(e - i);
+        g.per = carry_digits_per_thread((uint32_t)maxD);
+        const uint64_t chunk = (uint64_t)kCarryThreads * g.per;
+        const uint64_t L = 1ull << l;
+        for (size_t k = i; k < e; ++k) {
+            const pa_job& j = jobs[ok[k]];
+            const uint64_t D = digits_of(j.n);
+            JobDesc& d = h[k];
+            d.key = reinterpret_cast<const uint32_t*>(j.key);
+            d.c = reinterpret_cast<const uint32_t*>(j.c);
+            d.d = reinterpret_cast<const uint32_t*>(j.d);
+            d.seed_a = j.seed_a;
+            d.seed_b = j.seed_b;
+            d.n = j.n;
+            d.m = j.m;
+            d.num_digits = (uint32_t)D;
+            d.chunks = (uint32_t)((D + chunk - 1) / chunk);
+            d.out = j.out;
+            g.chunks = std::max(g.chunks, d.chunks);
+            g.key_bytes += (j.n + 7) / 8;
+            g.digits += D;
+            g.out_bytes += words_of(j.m) * 8;
+            offA[k] = bytes;
+            bytes += 2 * align256(kNumPrimes * 4ull * L);
+            offC[k] = bytes;
+            bytes += align256(8ull * d.chunks);
+        }
+        b->groups.push_back(g);
+        i = e;
+    }
+    b->launches = 0;
+    for (const auto& g : b->groups) b->launches += 3 * g.plan.P - 1 + 3;
+    hipError_t e;
+    if ((e = hipMalloc(&b->ws, bytes)) != hipSuccess ||
+        (e = hipMalloc(&b->d_jobs, sizeof(JobDesc) * h.size())) != hipSuccess) {
+        pa_batch_destroy(b);
+        return fail(ctx, PA_ENOMEM, "batch workspace allocation", e);
+    }
+    b->ws_bytes = bytes;
+    for (size_t k = 0; k < h.size(); ++k) {
+        const uint64_t L = 1ull << log2_len(h[k].n);
+        h[k].A = reinterpret_cast<uint32_t*>(b->ws + offA[k]);
+        h[k].B = reinterpret_cast<uint32_t*>(b->ws + offA[k] + align256(kNumPrimes * 4ull * L));
+        h[k].carry = reinterpret_cast<uint32_t*>(b->ws + offC[k]);
+    }
+    if ((e = hipMemcpy(b->d_jobs, h.data(), sizeof(JobDesc) * h.size(), hipMemcpyHostToDevice)) !=
+        hipSuccess) {
+        pa_batch_destroy(b);
+        return fail(ctx, PA_EDEVICE, "batch job table upload", e);
+    }
+    *out = b;
+    return PA_OK;
+}
+
+int pa_batch_run(pa_batch* b, void* stream)
+{
+    if (!b) return PA_EINVAL;
+    pa_ctx* ctx = b->ctx;
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    if (b->exec) {
+        PA_HIP(ctx, hipGraphLaunch(b->exec, (hipStream_t)stream));
+        return PA_OK;
+    }
+    return enqueue_batch(b, (hipStream_t)stream);
+}
+
+int pa_batch_capture(pa_batch* b, void* stream)
+{
+    if (!b) return PA_EINVAL;
+    pa_ctx* ctx = b->ctx;
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    PA_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_batch(b, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(ctx, PA_EDEVICE, "hipStreamEndCapture", e);
+    b->graph = g;
+    PA_HIP(ctx, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return PA_OK;
+}
+
+uint64_t pa_batch_bytes(const pa_batch* b)
+{
+    return b ? b->ws_bytes + sizeof(JobDesc) * b->valid : 0;
+}
+
+size_t pa_batch_size(const pa_batch* b) { return b ? b->valid : 0; }
+
+size_t pa_batch_launches(const pa_batch* b) { return b ? b->launches : 0; }
+
+int pa_hash_many(pa_ctx* ctx, pa_job* jobs, size_t count, void* stream)
+{
+    pa_batch* b = nullptr;
+    int rc = pa_batch_create(ctx, jobs, count, &b);
+    if (rc) return rc;
+    rc = pa_batch_run(b, stream);
+    const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    pa_batch_destroy(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(ctx, PA_EDEVICE, "hipStreamSynchronize", e);
+    return PA_OK;
 }
 
 }  // extern "C"
