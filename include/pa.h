@@ -174,6 +174,64 @@ void pa_batch_destroy(pa_batch *batch);
 /* create + run + wait + destroy; per-block status in jobs[i].status. */
 int pa_hash_many(pa_ctx *ctx, pa_job *jobs, size_t count, void *stream);
 
+/*
+ * Server: continuous hashing of a stream of requests on one GPU.  Requests are
+ * admitted in arrival order as soon as one of `slots` slots is free and their
+ * device footprint fits in `hbm_budget` bytes (allocated once at creation);
+ * admitted requests run concurrently on their slots' streams, so a request
+ * that arrives while others are on the GPU starts without waiting for them.
+ * The server owns its own context (twiddle tables stay on the device) and a
+ * scheduler thread; its functions may be called from any thread.
+ */
+typedef struct pa_server pa_server;
+
+typedef struct pa_server_opts {
+    uint64_t hbm_budget;  /* device bytes for requests in flight */
+    int slots;            /* requests on the device at once */
+    uint64_t max_n;       /* largest block accepted (<= PA_MAX_N) */
+} pa_server_opts;
+
+typedef struct pa_server_stats {
+    uint64_t completed, failed;
+    uint64_t bits;            /* input bits of completed requests */
+    uint64_t peak_inflight;   /* most requests on the device at once */
+    uint64_t peak_bytes;      /* most budget bytes in use at once */
+    double lat_p50_ms, lat_p99_ms, lat_mean_ms;   /* submit -> result ready */
+    double wall_s;            /* first submit -> last completion */
+} pa_server_stats;
+
+/* key/out of a request are device pointers (no host staging). */
+#define PA_SUBMIT_DEVICE 1
+
+/* PA_EINVAL if the budget cannot hold one request of max_n bits. */
+int pa_server_create(int device, const pa_server_opts *opts, pa_server **server);
+
+/* Queue one request.  Host pointers by default: key (ceil(n/64) words) must
+ * stay valid and out (ceil(m/64) words) untouched until the request is done.
+ * With PA_SUBMIT_DEVICE both are device pointers.  *ticket identifies it. */
+int pa_server_submit(pa_server *s, const uint64_t *key, uint64_t seed_a, uint64_t seed_b,
+                     uint64_t n, uint64_t m, uint64_t *out, int flags, uint64_t *ticket);
+
+/* Block until the request is done; its status and submit-to-result latency. */
+int pa_server_wait(pa_server *s, uint64_t ticket, int *status, double *latency_ms);
+
+/* Block until every request submitted so far is done. */
+int pa_server_drain(pa_server *s);
+
+int pa_server_get_stats(pa_server *s, pa_server_stats *stats);
+
+/*
+ * Open-loop load: submit jobs[i] (key/out/seeds/n/m; c and d must be NULL) at
+ * arrival_s[i] seconds after the call starts, from the calling thread, then
+ * wait for all.  latency_ms[i] and status[i] (either may be NULL) receive each
+ * request's submit-to-result latency and status.
+ */
+int pa_server_run_trace(pa_server *s, const pa_job *jobs, const double *arrival_s, size_t count,
+                        int flags, double *latency_ms, int *status);
+
+/* Finish what was submitted, then release everything. */
+void pa_server_destroy(pa_server *s);
+
 /* Size the workspace for blocks of up to n_max bits now. */
 int pa_reserve(pa_ctx *ctx, uint64_t n_max);
 

@@ -54,6 +54,21 @@ class _Job(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("status", ctypes.c_int)]
 
 
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int),
+                ("max_n", ctypes.c_uint64)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("bits", ctypes.c_uint64), ("peak_inflight", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64), ("lat_p50_ms", ctypes.c_double),
+                ("lat_p99_ms", ctypes.c_double), ("lat_mean_ms", ctypes.c_double),
+                ("wall_s", ctypes.c_double)]
+
+
+PA_SUBMIT_DEVICE = 1
+
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _u64 = ctypes.c_uint64
 
@@ -110,6 +125,27 @@ _lib.pa_batch_destroy.argtypes = [ctypes.c_void_p]
 _lib.pa_hash_many.restype = ctypes.c_int
 _lib.pa_hash_many.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Job), ctypes.c_size_t,
                               ctypes.c_void_p]
+
+_lib.pa_server_create.restype = ctypes.c_int
+_lib.pa_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(_ServerOpts),
+                                  ctypes.POINTER(ctypes.c_void_p)]
+_lib.pa_server_submit.restype = ctypes.c_int
+_lib.pa_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _u64, _u64, _u64, _u64,
+                                  ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+_lib.pa_server_wait.restype = ctypes.c_int
+_lib.pa_server_wait.argtypes = [ctypes.c_void_p, _u64, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_double)]
+_lib.pa_server_drain.restype = ctypes.c_int
+_lib.pa_server_drain.argtypes = [ctypes.c_void_p]
+_lib.pa_server_get_stats.restype = ctypes.c_int
+_lib.pa_server_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(_ServerStats)]
+_lib.pa_server_run_trace.restype = ctypes.c_int
+_lib.pa_server_run_trace.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Job),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_size_t,
+                                     ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int)]
+_lib.pa_server_destroy.restype = None
+_lib.pa_server_destroy.argtypes = [ctypes.c_void_p]
 
 MASK64 = (1 << 64) - 1
 
@@ -274,6 +310,87 @@ class Batch:
         if self.h:
             _lib.pa_batch_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """pa_server: continuous hashing of a request stream on one GPU."""
+
+    def __init__(self, hbm_budget: int, slots: int = 8, max_n: int = 10**8, device: int = 0):
+        opts = _ServerOpts(int(hbm_budget), int(slots), int(max_n))
+        h = ctypes.c_void_p()
+        rc = _lib.pa_server_create(int(device), ctypes.byref(opts), ctypes.byref(h))
+        if rc != PA_OK:
+            raise PAError(rc, pa_strerror(rc))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, key, seed_a: int, seed_b: int, n: int, m: int, out) -> int:
+        """key/out: device tensors (PA_SUBMIT_DEVICE) or host numpy uint64 arrays."""
+        t = ctypes.c_uint64()
+        if getattr(key, "is_cuda", False):
+            kp, op, flags = _dev_ptr(key, words(n), "key"), _dev_ptr(out, words(m), "out"), 1
+        else:
+            if not (isinstance(out, np.ndarray) and out.dtype == np.uint64
+                    and out.flags.c_contiguous and out.size >= words(m)):
+                raise ValueError("out: need a contiguous uint64 array of ceil(m/64) words")
+            key = _host_words(key, words(n), "key")
+            kp, op, flags = key.ctypes.data, out.ctypes.data, 0
+        rc = _lib.pa_server_submit(self.h, kp, seed_a & MASK64, seed_b & MASK64, n, m, op, flags,
+                                   ctypes.byref(t))
+        if rc != PA_OK:
+            raise PAError(rc, pa_strerror(rc))
+        self._keep[t.value] = (key, out)
+        return t.value
+
+    def wait(self, ticket: int) -> tuple[int, float]:
+        st, lat = ctypes.c_int(), ctypes.c_double()
+        rc = _lib.pa_server_wait(self.h, ticket, ctypes.byref(st), ctypes.byref(lat))
+        if rc != PA_OK:
+            raise PAError(rc, pa_strerror(rc))
+        self._keep.pop(ticket, None)
+        return st.value, lat.value
+
+    def drain(self):
+        _lib.pa_server_drain(self.h)
+        self._keep.clear()
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _lib.pa_server_get_stats(self.h, ctypes.byref(st))
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+    def run_trace(self, jobs, arrival_s, device: bool = True):
+        """Open-loop replay: jobs[i] (dicts as for Batch) submitted at
+        arrival_s[i] seconds; returns (latencies_ms, statuses)."""
+        arr = _job_array(jobs) if device else None
+        if not device:
+            raise ValueError("run_trace replays device-resident requests")
+        k = len(jobs)
+        t = (ctypes.c_double * k)(*[float(x) for x in arrival_s])
+        lat = (ctypes.c_double * k)()
+        st = (ctypes.c_int * k)()
+        rc = _lib.pa_server_run_trace(self.h, arr, t, k, PA_SUBMIT_DEVICE, lat, st)
+        if rc != PA_OK:
+            raise PAError(rc, pa_strerror(rc))
+        return list(lat), list(st)
+
+    def close(self):
+        if self.h:
+            _lib.pa_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

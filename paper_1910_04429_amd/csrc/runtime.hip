@@ -6,38 +6,9 @@
 #include <new>
 #include <vector>
 
-#include "../../include/pa.h"
-#include "kernels.h"
+#include "context.h"
 
 using namespace pa;
-
-struct pa_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;     // used by the synchronous entry points
-    // tables
-    uint2* rtw = nullptr;
-    uint32_t* pass_lo = nullptr;
-    uint32_t* pass_hi = nullptr;
-    // workspace, sized for cap_L / cap_D
-    uint64_t cap_L = 0, cap_D = 0;
-    uint32_t* A = nullptr;            // c-hat   [3][L]
-    uint32_t* B = nullptr;            // x-hat, then the product residues [3][L]
-    uint32_t* status = nullptr;       // carry state: [chunks] functions, [chunks] carries
-    // staging for the synchronous (host memory) entry points
-    uint64_t cap_words = 0;
-    uint64_t* d_key = nullptr;
-    uint64_t* d_c = nullptr;
-    uint64_t* d_d = nullptr;
-    uint64_t* d_out = nullptr;
-    // side streams (default priority) on which batch groups run concurrently
-    static constexpr int kSide = 4;
-    hipStream_t side[kSide] = {};
-    hipEvent_t fork = nullptr;
-    hipEvent_t join[kSide] = {};
-    hipEvent_t ev[2 * PA_PROFILE_MAX] = {};
-    bool have_events = false;
-    char err[512] = {0};
-};
 
 namespace {
 
@@ -453,6 +424,51 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
 }
 
 }  // namespace
+
+namespace pa {
+
+uint64_t block_workspace_bytes(uint64_t n)
+{
+    const uint64_t L = 1ull << log2_len(n);
+    return 2 * ((kNumPrimes * 4ull * L + 255) & ~255ull) + ((4ull * status_words(digits_of(n)) + 255) & ~255ull);
+}
+
+void block_layout(uint64_t n, uint8_t* base, BlockBufs* b)
+{
+    const uint64_t L = 1ull << log2_len(n);
+    const uint64_t arr = (kNumPrimes * 4ull * L + 255) & ~255ull;
+    b->A = reinterpret_cast<uint32_t*>(base);
+    b->B = reinterpret_cast<uint32_t*>(base + arr);
+    b->carry = reinterpret_cast<uint32_t*>(base + 2 * arr);
+}
+
+int enqueue_block(pa_ctx* ctx, const BlockBufs& b, hipStream_t stream)
+{
+    Plan pl;
+    if (!make_plan(log2_len(b.n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    Work w;
+    w.key = b.key;
+    w.c = b.c;
+    w.d = b.d;
+    w.seed_a = b.seed_a;
+    w.seed_b = b.seed_b;
+    w.n = b.n;
+    w.m = b.m;
+    w.A = b.A;
+    w.B = b.B;
+    w.carry = b.carry;
+    w.out = b.out;
+    w.chunks = chunks_of(digits_of(b.n));
+    w.per = carry_digits_per_thread((uint32_t)digits_of(b.n));
+    w.key_bytes = (b.n + 7) / 8;
+    w.digits = digits_of(b.n);
+    w.out_bytes = words_of(b.m) * 8;
+    return enqueue_plan(ctx, pl, w, stream);
+}
+
+int set_error(pa_ctx* ctx, int code, const char* what) { return fail(ctx, code, what); }
+
+}  // namespace pa
 
 struct pa_batch {
     pa_ctx* ctx = nullptr;

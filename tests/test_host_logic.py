@@ -1,0 +1,111 @@
+"""Host-side logic that needs no GPU: the server's HBM arena (admission by
+footprint) and the transform plan exported by the library."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import torch  # noqa: F401  (load torch's HIP runtime before libpa, as the binding does)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1910_04429_amd", "csrc")
+
+DRIVER = r"""
+#include <stdio.h>
+#include "arena.h"
+int main() {
+    unsigned long long size; if (scanf("%llu", &size) != 1) return 2;
+    pa::Arena a(size);
+    char op; unsigned long long x, y;
+    while (scanf(" %c", &op) == 1) {
+        if (op == 'a') { if (scanf("%llu", &x) != 1) return 2; uint64_t off = 0;
+            if (a.alloc(x, &off)) printf("ok %llu\n", (unsigned long long)off); else printf("full\n"); }
+        else if (op == 'f') { if (scanf("%llu %llu", &x, &y) != 2) return 2; a.release(x, y); printf("freed\n"); }
+        else if (op == 'p') { printf("peak %llu\n", (unsigned long long)a.peak()); }
+    }
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def arena_bin(tmp_path_factory):
+    d = tmp_path_factory.mktemp("arena")
+    src, exe = d / "drv.cpp", d / "drv"
+    src.write_text(DRIVER)
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+def run(exe, size, ops):
+    text = f"{size}\n" + "\n".join(ops) + "\n"
+    out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout
+    return out.split("\n")[:-1]
+
+
+def r256(x):
+    return (x + 255) // 256 * 256
+
+
+def test_arena_random_alloc_free_never_overlaps(arena_bin):
+    """Random allocations and frees: every block is 256-aligned, in range and
+    disjoint from every live block; the reported peak matches a model."""
+    rng = np.random.default_rng(0)
+    size = 1 << 24
+    ops, live, used, peak = [], [], 0, 0
+    for _ in range(150):
+        if live and rng.random() < 0.45:
+            off, sz = live.pop(int(rng.integers(len(live))))
+            ops.append(f"f {off} {sz}")
+            used -= sz
+            continue
+        want = int(rng.integers(1, 1 << 21))
+        ops.append(f"a {want}")
+        res = run(arena_bin, size, ops)[-1]
+        if not res.startswith("ok"):
+            ops.pop()                      # a refused request changes nothing
+            continue
+        off, sz = int(res.split()[1]), r256(want)
+        assert off % 256 == 0 and off + sz <= size
+        for o2, s2 in live:
+            assert off + sz <= o2 or o2 + s2 <= off, "overlapping blocks"
+        live.append((off, sz))
+        used += sz
+        peak = max(peak, used)
+    assert run(arena_bin, size, ops + ["p"])[-1] == f"peak {peak}"
+
+
+def test_arena_coalesces_back_to_one_block(arena_bin):
+    size = 1 << 20
+    ops = [f"a {4096}" for _ in range(256)]          # fill exactly
+    ops.append("a 1")                                 # no room
+    offs = list(range(0, size, 4096))
+    rng = np.random.default_rng(1)
+    for o in rng.permutation(offs):
+        ops.append(f"f {o} 4096")
+    ops.append(f"a {size}")                           # whole range again
+    out = run(arena_bin, size, ops)
+    assert out[255].startswith("ok") and out[256] == "full"
+    assert out[-1] == "ok 0"
+
+
+def test_arena_first_fit_and_merge(arena_bin):
+    size = 10 * 256
+    out = run(arena_bin, size, ["a 512", "a 512", "a 512", "f 512 512", "a 1024",
+                                "f 0 512", "a 1024"])
+    # after freeing [512, 1024) the free pieces [512, 1024) and [1536, 2560) are
+    # apart; a 1024-byte request takes the first piece that fits ...
+    assert out[0] == "ok 0" and out[1] == "ok 512" and out[2] == "ok 1024"
+    assert out[4] == "ok 1536"
+    # ... and freeing [0, 512) merges with [512, 1024) into a 1024-byte piece
+    assert out[6] == "ok 0"
+
+
+def test_plan_lengths_cover_the_linear_convolution():
+    import paper_1910_04429_amd as pa
+    for n in [1, 31, 32, 33, 1000, 65_536, 1_000_000, 10**7, 10**8, pa.PA_MAX_N]:
+        L = pa.pa_transform_length(n)
+        D = (n + 31) // 32
+        assert L >= 2 * D - 1 and L & (L - 1) == 0 and L <= 1 << 25
+        assert L == 64 or L // 2 < 2 * D - 1
+        assert pa.pa_workspace_bytes(n) >= 2 * 3 * 4 * L
