@@ -4,11 +4,14 @@ One step = one hash of a single n = 10^8-bit block (m = 4*10^7 output bits,
 key / multiplier / addend uniform random from workload seed 2), run through the
 device-resident entry point with the key already in HBM.  Prints one JSON line:
 throughput in Mbps of input key, the roofline of the dominant kernel (timed with
-HIP events on the stream it runs on), and the CPU oracle timed on this host.
+HIP events on the stream it runs on), the CPU oracle timed on this host, and,
+beside them, the n = 10^6 block, the 256-block batch (batched vs plain) and the
+served stream (p50 / p99 latency at three offered loads).
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -31,7 +34,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="n1e8", choices=["n1e6", "n1e7", "n1e8"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the n=1e6, batched and served measurements")
     ap.add_argument("--profile-runs", type=int, default=5)
+    ap.add_argument("--served-requests", type=int, default=2000)
     return ap.parse_args()
 
 
@@ -68,6 +74,106 @@ def cpu_baseline(blk, key):
                          f"{os.cpu_count()} logical CPUs"}
 
 
+def time_single(pa, ctx, torch, blk, steps, warmup):
+    """ms per block for one block through pa_hash_async, key resident."""
+    d_key = torch.from_numpy(blk.key().view(np.int64)).cuda()
+    d_out = torch.zeros(pa.words(blk.m), dtype=torch.int64, device="cuda")
+    pa.pa_reserve(ctx, blk.n)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        pa.pa_hash_async(ctx, d_key, blk.seed_a, blk.seed_b, blk.n, blk.m, d_out, stream)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record(stream)
+    for _ in range(steps):
+        pa.pa_hash_async(ctx, d_key, blk.seed_a, blk.seed_b, blk.n, blk.m, d_out, stream)
+    e.record(stream)
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps, d_key, d_out
+
+
+def batched_vs_plain(pa, ctx, torch, workloads):
+    """256 blocks, n log-uniform in [1e5, 1e7]: one captured batch vs the same
+    blocks hashed one at a time."""
+    blocks = workloads.batch_blocks(3, 256)
+    bits = sum(b.n for b in blocks)
+    jobs = [{"key": torch.from_numpy(b.key().view(np.int64)).cuda(),
+             "out": torch.zeros(workloads.words(b.m), dtype=torch.int64, device="cuda"),
+             "n": b.n, "m": b.m, "seed_a": b.seed_a, "seed_b": b.seed_b} for b in blocks]
+    batch = pa.Batch(ctx, jobs)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    try:
+        batch.capture()
+        for _ in range(3):
+            batch.run()
+        torch.cuda.synchronize()
+        s.record()
+        reps = 10
+        for _ in range(reps):
+            batch.run()
+        e.record()
+        torch.cuda.synchronize()
+        ms_batch = s.elapsed_time(e) / reps
+    finally:
+        batch.close()
+    pa.pa_reserve(ctx, max(b.n for b in blocks))
+    for b, j in zip(blocks, jobs):
+        pa.pa_hash_async(ctx, j["key"], b.seed_a, b.seed_b, b.n, b.m, j["out"])
+    torch.cuda.synchronize()
+    s.record()
+    for b, j in zip(blocks, jobs):
+        pa.pa_hash_async(ctx, j["key"], b.seed_a, b.seed_b, b.n, b.m, j["out"])
+    e.record()
+    torch.cuda.synchronize()
+    ms_plain = s.elapsed_time(e)
+    return {"workload": "256 blocks, n log-uniform in [1e5, 1e7], m = round(r n), "
+                        "r uniform in [0.05, 0.5], seed 3",
+            "bits": bits, "batched_ms": round(ms_batch, 3),
+            "batched_mbps": round(bits / (ms_batch * 1e-3) / 1e6, 1),
+            "plain_ms": round(ms_plain, 3),
+            "plain_mbps": round(bits / (ms_plain * 1e-3) / 1e6, 1),
+            "batch_runs": "captured HIP graph, groups by transform length on 4 streams"}
+
+
+def served(pa, torch, workloads, count):
+    """Poisson stream of requests, n log-uniform in [1e6, 1e8], m = 0.3 n.
+    Saturated throughput C first (all requests at t = 0), then offered loads
+    rho C for rho in (0.5, 0.8, 0.95)."""
+    blocks, unit_times = workloads.served_requests(4, count, rate_per_s=1.0)
+    pool = torch.from_numpy(workloads.key_bits(workloads.seeds_of(4)[0], 10**8)
+                            .view(np.int64)).cuda()
+    outs = [torch.zeros(workloads.words(b.m), dtype=torch.int64, device="cuda") for b in blocks]
+    jobs = [{"key": pool, "out": o, "n": b.n, "m": b.m, "seed_a": b.seed_a,
+             "seed_b": b.seed_b} for b, o in zip(blocks, outs)]
+    mean_n = sum(b.n for b in blocks) / len(blocks)
+    budget = 16 << 30
+    res = {"workload": f"{count} requests, n log-uniform in [1e6, 1e8], m = 0.3 n, "
+                       "Poisson arrivals, seed 4; keys are prefixes of one resident "
+                       "1e8-bit key, seeds per request",
+           "hbm_budget_bytes": budget, "slots": 8, "loads": []}
+    with pa.Server(hbm_budget=budget, slots=8, max_n=10**8) as srv:
+        lat, st = srv.run_trace(jobs[:64], [0.0] * 64)            # warm-up
+    with pa.Server(hbm_budget=budget, slots=8, max_n=10**8) as srv:
+        lat, st = srv.run_trace(jobs, [0.0] * len(jobs))
+        sat = srv.stats()
+    C = sat["bits"] / sat["wall_s"]
+    res["saturated_mbps"] = round(C / 1e6, 1)
+    for rho in (0.5, 0.8, 0.95):
+        rate = rho * C / mean_n                                     # requests per second
+        times = np.asarray(unit_times) / rate
+        with pa.Server(hbm_budget=budget, slots=8, max_n=10**8) as srv:
+            lat, st = srv.run_trace(jobs, times)
+            s = srv.stats()
+        ok = all(x == pa.PA_OK for x in st)
+        res["loads"].append({"rho": rho, "offered_mbps": round(rho * C / 1e6, 1),
+                             "mbps": round(s["bits"] / s["wall_s"] / 1e6, 1),
+                             "p50_ms": round(s["lat_p50_ms"], 3),
+                             "p99_ms": round(s["lat_p99_ms"], 3),
+                             "mean_ms": round(s["lat_mean_ms"], 3),
+                             "peak_inflight": s["peak_inflight"], "all_ok": ok})
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -81,33 +187,16 @@ def main():
 
     blk = workloads.single(args.workload)
     key = blk.key()
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(0)
     ctx = pa.pa_init(0)
-    d_key = torch.from_numpy(key.view(np.int64)).to(dev)
-    d_out = torch.zeros(pa.words(blk.m), dtype=torch.int64, device=dev)
-    pa.pa_reserve(ctx, blk.n)
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        pa.pa_hash_async(ctx, d_key, blk.seed_a, blk.seed_b, blk.n, blk.m, d_out, stream)
-    torch.cuda.synchronize()
-
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record(stream)
-    for _ in range(args.steps):
-        pa.pa_hash_async(ctx, d_key, blk.seed_a, blk.seed_b, blk.n, blk.m, d_out, stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
+    ms_per_step, d_key, d_out = time_single(pa, ctx, torch, blk, args.steps, args.warmup)
     wall = time.perf_counter() - t0
-    ms = start.elapsed_time(stop)
-    ms_per_step = ms / args.steps
-    mbps = blk.n * args.steps / (ms / 1e3) / 1e6
+    mbps = blk.n / (ms_per_step * 1e-3) / 1e6
     gpu_out = d_out.cpu().numpy().view(np.uint64).copy()
 
     # per-launch HIP events, same stream, outside the timed region
+    stream = torch.cuda.current_stream()
     kinds = {}
     for _ in range(args.profile_runs):
         for rec in pa.pa_hash_profile(ctx, d_key, blk.seed_a, blk.seed_b, blk.n, blk.m,
@@ -121,14 +210,22 @@ def main():
     avg_ms = d["ms"] / d["launches"]
     avg_bytes = d["bytes"] / d["launches"]
     achieved = avg_bytes / (avg_ms / 1e3) / 1e9
-    traffic = measured_traffic()
     roofline = {"bound": "hbm", "kernel": f"k_pass ({dom})", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
+                "traffic": measured_traffic(), "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": int(avg_bytes)}
     breakdown = {k: {"ms_per_step": round(v["ms"] / args.profile_runs, 4),
                      "launches_per_step": v["launches"] // args.profile_runs}
                  for k, v in kinds.items()}
+
+    extra = {}
+    if not args.no_extra:
+        b6 = workloads.single("n1e6")
+        ms6, _, _ = time_single(pa, ctx, torch, b6, 200, 20)
+        extra["n1e6"] = {"ms_per_block": round(ms6, 4), "mbps": round(b6.n / (ms6 * 1e-3) / 1e6, 1),
+                         "paper_mbps_i9": 262.13}
+        extra["batched"] = batched_vs_plain(pa, ctx, torch, workloads)
+        extra["served"] = served(pa, torch, workloads, args.served_requests)
 
     cpu = None
     bit_exact = None
@@ -153,6 +250,7 @@ def main():
         "roofline": roofline,
         "kernels": breakdown,
         "cpu_baseline": cpu,
+        **extra,
         "host_wall_s_timed_region": round(wall, 4),
     }
     print(json.dumps(line), flush=True)

@@ -47,8 +47,49 @@ constexpr int bitrev_c(int x, int bits)
     return r;
 }
 
-// Digit t of the operand described by the pass source (0 beyond the top digit).
-__device__ __forceinline__ uint32_t source_digit(const PassArgs& a, uint32_t t)
+// What one workgroup reads and writes: the scalar fields of the pass, or the
+// fields of its block in batch mode.  Kept apart from the kernel argument so
+// the argument is never copied to private memory.
+struct BlockView {
+    uint32_t* data;
+    const uint32_t* other;
+    const uint32_t* digits;
+    uint64_t seed;
+    uint64_t n;
+    uint32_t num_digits;
+    uint32_t store_limit;
+    int src;
+};
+
+__device__ __forceinline__ BlockView block_view(const PassArgs& a)
+{
+    BlockView v{a.data, a.other, a.digits, a.seed, a.n, a.num_digits, a.store_limit, a.src};
+    if (a.jobs) {
+        const JobDesc& j = a.jobs[blockIdx.z];
+        v.n = j.n;
+        v.num_digits = j.num_digits;
+        v.data = (a.role == kRoleMul) ? j.A : j.B;
+        v.other = j.A;
+        if (a.src != kSrcArray) {             // first pass: the operand's digits
+            if (a.role == kRoleKey) {
+                v.src = kSrcDigits;
+                v.digits = j.key;
+            } else if (j.c) {
+                v.src = kSrcDigits;
+                v.digits = j.c;
+            } else {
+                v.src = kSrcSeed;
+                v.seed = j.seed_a;
+            }
+        }
+        if (a.limit_to_digits)
+            v.store_limit = (j.num_digits + 3u) & ~3u;
+    }
+    return v;
+}
+
+// Digit t of the operand described by the block's source (0 beyond the top digit).
+__device__ __forceinline__ uint32_t source_digit(const BlockView& a, uint32_t t)
 {
     if (t >= a.num_digits)
         return 0;
@@ -244,41 +285,16 @@ __device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int logC, int s, 
     return g;
 }
 
-// Batch mode: take the block's pointers, sizes and sources from its job.
-__device__ __forceinline__ void bind_job(PassArgs& a)
-{
-    const JobDesc& j = a.jobs[blockIdx.z];
-    a.n = j.n;
-    a.num_digits = j.num_digits;
-    a.data = (a.role == kRoleMul) ? j.A : j.B;
-    a.other = j.A;
-    if (a.src != kSrcArray) {                 // first pass: the operand's digits
-        if (a.role == kRoleKey) {
-            a.src = kSrcDigits;
-            a.digits = j.key;
-        } else if (j.c) {
-            a.src = kSrcDigits;
-            a.digits = j.c;
-        } else {
-            a.src = kSrcSeed;
-            a.seed = j.seed_a;
-        }
-    }
-    if (a.limit_to_digits)
-        a.store_limit = (j.num_digits + 3u) & ~3u;
-}
-
-__global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
+__global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
 {
     extern __shared__ uint32_t sm[];          // 4 << logN bytes
-    if (a.jobs)
-        bind_job(a);
+    const BlockView bv = block_view(a);
 
     const int pi = blockIdx.y;
     const uint32_t p = kPrimes[pi], pneg = kNegInv[pi];
     const uint2* twf = a.rtw + pi * 64;       // omega_64^e, e < 32
     const uint2* twi = twf + 32;              // omega_64^{-e}
-    uint32_t* data = a.data + ((size_t)pi << a.logL);
+    uint32_t* data = bv.data + ((size_t)pi << a.logL);
 
     const int logN = a.logN;                  // tile residues
     const int N = 1 << logN;
@@ -303,13 +319,13 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
             pos = blk0 + e;
         }
         uint4 v;
-        if (a.src == kSrcArray) {
+        if (bv.src == kSrcArray) {
             v = *reinterpret_cast<const uint4*>(data + pos);
         } else {
-            v.x = freduce32(source_digit(a, pos + 0), p);
-            v.y = freduce32(source_digit(a, pos + 1), p);
-            v.z = freduce32(source_digit(a, pos + 2), p);
-            v.w = freduce32(source_digit(a, pos + 3), p);
+            v.x = freduce32(source_digit(bv, pos + 0), p);
+            v.y = freduce32(source_digit(bv, pos + 1), p);
+            v.z = freduce32(source_digit(bv, pos + 2), p);
+            v.w = freduce32(source_digit(bv, pos + 3), p);
         }
         *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
     }
@@ -330,7 +346,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
         if (a.mode == kFused) {
             // Pointwise product with the pre-scaled c-hat (same layout), then
             // the inverse of this pass.
-            const uint32_t* other = a.other + ((size_t)pi << a.logL);
+            const uint32_t* other = bv.other + ((size_t)pi << a.logL);
             for (int u = threadIdx.x; u < nq; u += blockDim.x) {
                 const uint32_t e = (uint32_t)u << 2;
                 const uint4 cv = *reinterpret_cast<const uint4*>(other + blk0 + e);
@@ -369,7 +385,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs a)
             v.z = fmul_shoup(v.z, w, q, p);
             v.w = fmul_shoup(v.w, w, q, p);
         }
-        if (pos < a.store_limit)
+        if (pos < bv.store_limit)
             *reinterpret_cast<uint4*>(data + pos) = v;
     }
 }
