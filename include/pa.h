@@ -123,6 +123,26 @@ int pa_hash_profile(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_
                     uint64_t n, uint64_t m, uint64_t *d_out, void *stream, pa_profile *prof);
 
 /*
+ * Cached multiplier (opt-in).  When the same multiplier c is used for many
+ * blocks of one size n, its transform can be computed once and kept on the
+ * device; each block then needs two transforms instead of three.  The paper
+ * does not say whether g may be reused across blocks (Section 2.2 has it
+ * chosen at random and publicly); reuse is the caller's security decision.
+ *   pa_mul_create: transform c (expanded from seed_a, or the device words d_c,
+ *     which must be odd) for blocks of n bits, queued on `stream`.
+ *   pa_hash_mul_async: hash the device key d_key (ceil(n/64) words) with that
+ *     c and the addend of seed_b; m output bits into d_out.  Same ordering
+ *     rules as pa_hash_async (the context's workspace is reused).
+ *   pa_mul_destroy: waits for the device, then frees the spectrum.
+ */
+typedef struct pa_mul pa_mul;
+int pa_mul_create(pa_ctx *ctx, uint64_t seed_a, const uint64_t *d_c, uint64_t n, void *stream,
+                  pa_mul **mul);
+int pa_hash_mul_async(pa_ctx *ctx, const pa_mul *mul, const uint64_t *d_key, uint64_t seed_b,
+                      uint64_t m, uint64_t *d_out, void *stream);
+void pa_mul_destroy(pa_mul *mul);
+
+/*
  * Batches: many blocks of uneven n in one sequence of launches.  Blocks are
  * grouped by transform length; every kernel of a group runs once for all of
  * the group's blocks.  All pointers in a pa_job are device memory.

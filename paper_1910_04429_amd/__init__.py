@@ -147,6 +147,15 @@ _lib.pa_server_run_trace.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Job),
 _lib.pa_server_destroy.restype = None
 _lib.pa_server_destroy.argtypes = [ctypes.c_void_p]
 
+_lib.pa_mul_create.restype = ctypes.c_int
+_lib.pa_mul_create.argtypes = [ctypes.c_void_p, _u64, ctypes.c_void_p, _u64, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_void_p)]
+_lib.pa_hash_mul_async.restype = ctypes.c_int
+_lib.pa_hash_mul_async.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _u64, _u64,
+                                   ctypes.c_void_p, ctypes.c_void_p]
+_lib.pa_mul_destroy.restype = None
+_lib.pa_mul_destroy.argtypes = [ctypes.c_void_p]
+
 MASK64 = (1 << 64) - 1
 
 
@@ -237,6 +246,26 @@ def pa_hash_profile(ctx, d_key, seed_a: int, seed_b: int, n: int, m: int, d_out,
     return [{"kind": KERNEL_KINDS.get(prof.kind[i], str(prof.kind[i])),
              "ms": float(prof.ms[i]), "bytes": int(prof.bytes[i])}
             for i in range(prof.count)]
+
+
+def pa_mul_create(ctx, seed_a: int, n: int, c=None, stream=None):
+    """Transform the multiplier once (opt-in reuse across blocks of n bits)."""
+    h = ctypes.c_void_p()
+    cp = _dev_ptr(c, words(n), "c") if c is not None else None
+    _check(ctx, _lib.pa_mul_create(ctx, seed_a & MASK64, cp, n, _stream_handle(stream),
+                                   ctypes.byref(h)))
+    return h
+
+
+def pa_hash_mul_async(ctx, mul, d_key, seed_b: int, n: int, m: int, d_out, stream=None) -> None:
+    _check(ctx, _lib.pa_hash_mul_async(ctx, mul, _dev_ptr(d_key, words(n), "d_key"),
+                                       seed_b & MASK64, m, _dev_ptr(d_out, words(m), "d_out"),
+                                       _stream_handle(stream)))
+
+
+def pa_mul_destroy(mul) -> None:
+    if mul:
+        _lib.pa_mul_destroy(mul)
 
 
 def pa_reserve(ctx, n_max: int) -> None:

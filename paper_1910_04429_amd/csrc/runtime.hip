@@ -277,6 +277,8 @@ struct Work {
     uint32_t chunks = 0;               // grid width of the carry kernels
     int per = 4;                       // carry digits per thread
     uint64_t key_bytes = 0, digits = 0, out_bytes = 0;
+    bool have_chat = false;            // A already holds c-hat (cached multiplier)
+    bool only_chat = false;            // transform c into A and stop
 };
 
 // Queue every kernel of the hash (or of one batch group) on `stream`.
@@ -306,7 +308,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     };
     const uint32_t limit = (uint32_t)((digits_of(w.n) + 3) & ~3ull);
 
-    for (int i = 0; i < P; ++i) {                           // c-hat
+    for (int i = 0; i < P && !w.have_chat; ++i) {          // c-hat
         PassArgs a = base;
         a.role = kRoleMul;
         a.data = w.A;
@@ -332,6 +334,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
         const uint64_t in = (i == 0) ? (w.c ? w.key_bytes : 0) : arr;
         PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + arr, launch_pass(a, stream, batch));
     }
+    if (w.only_chat) return PA_OK;
     for (int i = 0; i < P; ++i) {                           // x-hat, pointwise, last inverse pass
         PassArgs a = base;
         a.role = kRoleKey;
@@ -754,6 +757,97 @@ int pa_hash_ex(pa_ctx* ctx, const uint64_t* key, const uint64_t* c, const uint64
 {
     if (!c || !d) return ctx ? fail(ctx, PA_EINVAL, "null operand") : PA_EINVAL;
     return hash_host(ctx, key, c, d, 0, 0, n, m, out);
+}
+
+struct pa_mul {
+    pa_ctx* ctx;
+    uint64_t n;
+    uint32_t* A;      // c-hat for blocks of n bits, scaled by 2^32 / L
+};
+
+int pa_mul_create(pa_ctx* ctx, uint64_t seed_a, const uint64_t* d_c, uint64_t n, void* stream,
+                  pa_mul** out)
+{
+    int rc = check_sizes(ctx, n, 1);
+    if (rc) return rc;
+    if (!out) return fail(ctx, PA_EINVAL, "null output handle");
+    *out = nullptr;
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    if (d_c) {
+        uint64_t w0 = 0;
+        PA_HIP(ctx, hipMemcpy(&w0, d_c, 8, hipMemcpyDeviceToHost));
+        if ((w0 & 1) == 0) return fail(ctx, PA_EINVAL, "multiplier c must be odd");
+    }
+    Plan pl;
+    if (!make_plan(log2_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    pa_mul* mh = new (std::nothrow) pa_mul;
+    if (!mh) return PA_ENOMEM;
+    mh->ctx = ctx;
+    mh->n = n;
+    mh->A = nullptr;
+    const uint64_t L = 1ull << pl.l;
+    hipError_t e = hipMalloc(&mh->A, kNumPrimes * 4ull * L);
+    if (e != hipSuccess) {
+        delete mh;
+        return fail(ctx, PA_ENOMEM, "multiplier spectrum allocation", e);
+    }
+    Work w;
+    w.c = reinterpret_cast<const uint32_t*>(d_c);
+    w.seed_a = seed_a;
+    w.n = n;
+    w.m = 1;
+    w.A = mh->A;
+    w.only_chat = true;
+    w.key_bytes = (n + 7) / 8;
+    w.digits = digits_of(n);
+    rc = enqueue_plan(ctx, pl, w, (hipStream_t)stream);
+    if (rc) {
+        (void)hipFree(mh->A);
+        delete mh;
+        return rc;
+    }
+    *out = mh;
+    return PA_OK;
+}
+
+int pa_hash_mul_async(pa_ctx* ctx, const pa_mul* mh, const uint64_t* d_key, uint64_t seed_b,
+                      uint64_t m, uint64_t* d_out, void* stream)
+{
+    if (!mh) return ctx ? fail(ctx, PA_EINVAL, "null multiplier handle") : PA_EINVAL;
+    int rc = check_sizes(ctx, mh->n, m);
+    if (rc) return rc;
+    if (!d_key || !d_out) return fail(ctx, PA_EINVAL, "null key or output pointer");
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    rc = ensure_workspace(ctx, mh->n);
+    if (rc) return rc;
+    Plan pl;
+    if (!make_plan(log2_len(mh->n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    const uint64_t n = mh->n;
+    Work w;
+    w.key = reinterpret_cast<const uint32_t*>(d_key);
+    w.seed_b = seed_b;
+    w.n = n;
+    w.m = m;
+    w.A = mh->A;
+    w.B = ctx->B;
+    w.carry = ctx->status;
+    w.out = d_out;
+    w.chunks = chunks_of(digits_of(n));
+    w.per = carry_digits_per_thread((uint32_t)digits_of(n));
+    w.key_bytes = (n + 7) / 8;
+    w.digits = digits_of(n);
+    w.out_bytes = words_of(m) * 8;
+    w.have_chat = true;
+    return enqueue_plan(ctx, pl, w, (hipStream_t)stream);
+}
+
+void pa_mul_destroy(pa_mul* mh)
+{
+    if (!mh) return;
+    (void)hipSetDevice(mh->ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(mh->A);
+    delete mh;
 }
 
 void pa_batch_destroy(pa_batch* b)
