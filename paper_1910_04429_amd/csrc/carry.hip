@@ -95,17 +95,15 @@ __device__ __forceinline__ void crt(uint32_t r0, uint32_t r1, uint32_t r2, uint3
     z2 = (uint32_t)hi;
 }
 
-// Chunk-local digit i in [-2, kChunk + 2) <-> LDS slot, padded so that
-// threads reading consecutive runs of kPer digits hit distinct banks.
+// Chunk-local digit i in [0, kChunk + 2) <-> LDS slot of the resolved digit,
+// padded so that threads writing consecutive runs of kPer digits hit distinct
+// banks.
 template <int kPer>
 __device__ __forceinline__ int slot(int i)
 {
-    const int j = i + 2;
-    return j + j / kPer;
+    return i + i / kPer;
 }
 
-// kApply = false: write the chunk's carry function.  kApply = true: resolve the
-// chunk with its carry-in and write its output words.
 // Batch mode: take the block's sizes, addend, state and output from its job.
 __device__ __forceinline__ void bind_job(CarryArgs& a, uint32_t job)
 {
@@ -127,6 +125,21 @@ __device__ __forceinline__ void bind_job(CarryArgs& a, uint32_t job)
     a.chunks = j.chunks;
 }
 
+// Residues of digit k (0 outside [0, D)).
+__device__ __forceinline__ void load_res(const CarryArgs& a, int64_t k, uint32_t& r0, uint32_t& r1,
+                                         uint32_t& r2)
+{
+    if (k < 0 || k >= (int64_t)a.num_digits) {
+        r0 = r1 = r2 = 0;
+        return;
+    }
+    r0 = a.res[k];
+    r1 = a.res[(size_t)a.L + k];
+    r2 = a.res[2 * (size_t)a.L + k];
+}
+
+// kApply = false: write the chunk's carry function.  kApply = true: resolve the
+// chunk with its carry-in and write its output words.
 template <int kPer, bool kApply>
 __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
 {
@@ -136,9 +149,7 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
             return;
     }
     constexpr int kChunk = kCarryThreads * kPer;
-    constexpr int kSpan = kChunk + 4;                      // digits -2 .. kChunk+1
-    constexpr int kSlots = kSpan + kSpan / kPer + 1;
-    __shared__ uint32_t res[kNumPrimes][kSlots];
+    constexpr int kSlots = kChunk + 2 + (kChunk + 2) / kPer + 1;
     __shared__ uint32_t val[kSlots];
     __shared__ uint32_t scan[kCarryThreads];
 
@@ -147,37 +158,50 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     const int64_t k0 = (int64_t)chunk * kChunk;
     const uint32_t D = a.num_digits;
 
-    // residues of digits k0-2 .. k0+kChunk+1 (0 outside [0, D))
-    for (int i = tid; i < kSpan; i += kCarryThreads) {
-        const int64_t k = k0 - 2 + i;
-        const bool in = k >= 0 && k < (int64_t)D;
-#pragma unroll
-        for (int pi = 0; pi < kNumPrimes; ++pi)
-            res[pi][slot<kPer>(i - 2)] = in ? a.res[(size_t)pi * a.L + (size_t)k] : 0u;
-    }
-    __syncthreads();
-
     // column sums of this thread's kPer digits (and, for the last thread, the
     // two digits past the chunk, which it resolves with the chunk's carry-out)
     constexpr int kExtra = 2;
     uint64_t s[kPer + kExtra];
     const int first = tid * kPer;
     const int count = kPer + (tid == kCarryThreads - 1 ? kExtra : 0);
+    const int64_t kf = k0 + first;
+    // this thread's residues, 16-byte loads when the run lies inside [0, D)
+    uint32_t r[3][kPer];
+    if (kf + kPer <= (int64_t)D) {
+#pragma unroll
+        for (int pi = 0; pi < kNumPrimes; ++pi) {
+            const uint4* src = reinterpret_cast<const uint4*>(a.res + (size_t)pi * a.L + kf);
+#pragma unroll
+            for (int v = 0; v < kPer / 4; ++v) {
+                const uint4 q = src[v];
+                r[pi][4 * v] = q.x;
+                r[pi][4 * v + 1] = q.y;
+                r[pi][4 * v + 2] = q.z;
+                r[pi][4 * v + 3] = q.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) load_res(a, kf + i, r[0][i], r[1][i], r[2][i]);
+    }
     {
-        uint32_t z0, z1, z2;
-        crt(res[0][slot<kPer>(first - 2)], res[1][slot<kPer>(first - 2)],
-            res[2][slot<kPer>(first - 2)], z0, z1, z2);
+        uint32_t z0, z1, z2, q0, q1, q2;
+        load_res(a, kf - 2, q0, q1, q2);
+        crt(q0, q1, q2, z0, z1, z2);
         uint32_t prev2_hi = z2;
-        crt(res[0][slot<kPer>(first - 1)], res[1][slot<kPer>(first - 1)],
-            res[2][slot<kPer>(first - 1)], z0, z1, z2);
+        load_res(a, kf - 1, q0, q1, q2);
+        crt(q0, q1, q2, z0, z1, z2);
         uint32_t prev_mid = z1, prev_hi = z2;
 #pragma unroll
         for (int i = 0; i < kPer + kExtra; ++i) {
             if (i < count) {
-                const int li = first + i;
-                crt(res[0][slot<kPer>(li)], res[1][slot<kPer>(li)], res[2][slot<kPer>(li)], z0,
-                    z1, z2);
-                const int64_t k = k0 + li;
+                if (i < kPer) {
+                    crt(r[0][i], r[1][i], r[2][i], z0, z1, z2);
+                } else {
+                    load_res(a, kf + i, q0, q1, q2);
+                    crt(q0, q1, q2, z0, z1, z2);
+                }
+                const int64_t k = kf + i;
                 const uint32_t d = (k < (int64_t)D) ? addend_digit(a, (uint32_t)k) : 0u;
                 s[i] = (k < (int64_t)D) ? (uint64_t)z0 + prev_mid + prev2_hi + d : 0ull;
                 prev2_hi = prev_hi;

@@ -16,6 +16,10 @@ namespace pa {
 
 constexpr int kNumPrimes = 3;
 constexpr int kLogMaxLen = 25;                 // min 2-adicity of the primes
+// Every transform length divides kOrder = 3 * 2^25, which divides p - 1 for
+// each prime (quotients 20, 18 and 21): one root of unity of order kOrder per
+// prime generates the twiddles of every length 2^k and 3 * 2^k.
+constexpr uint32_t kOrder = 3u << kLogMaxLen;
 constexpr uint32_t kPrimes[kNumPrimes] = {
     2013265921u,  // 15 * 2^27 + 1
     1811939329u,  // 27 * 2^26 + 1
@@ -62,6 +66,9 @@ static_assert(kPrimes[0] > kPrimes[1] && kPrimes[0] < 2 * (uint64_t)kPrimes[1],
 static_assert(kPrimes[0] < kPrimes[2] && kPrimes[1] < kPrimes[2],
               "Garner step assumes p0, p1 < p2");
 static_assert((uint32_t)(kNegInv[0] * kPrimes[0]) == 0xFFFFFFFFu, "Montgomery constant");
+static_assert((kPrimes[0] - 1) % kOrder == 0 && (kPrimes[1] - 1) % kOrder == 0 &&
+                  (kPrimes[2] - 1) % kOrder == 0,
+              "every prime has roots of unity of order 3 * 2^25");
 
 // ---------------------------------------------------------------------------
 // Canonical residues in [0, p), p < 2^31.

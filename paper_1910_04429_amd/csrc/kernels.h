@@ -15,12 +15,15 @@ constexpr int kStridedMaxLog = 9;            // strided passes: <= 512 rows
 constexpr int kMaxSteps = 4;
 constexpr int kPassThreads = 256;
 
+constexpr int kRootHi = (int)(kOrder >> 12);   // 24576 high-table entries
+constexpr int kRtw = 66;                         // small-root table entries per prime
+
 // Device tables shared by every plan, one block per prime.
 struct Tables {
-    // Montgomery form of omega_{2^25}^i (i < 4096) and omega_{2^25}^{4096 j}
-    // (j < 8192): any power omega^E = lo[E & 4095] * hi[E >> 12].
+    // Montgomery form of w^i (i < 4096) and w^{4096 j} (j < kRootHi), w the
+    // root of order kOrder: any power w^E = lo[E & 4095] * hi[E >> 12].
     const uint32_t* pass_lo;  // [kNumPrimes][4096]
-    const uint32_t* pass_hi;  // [kNumPrimes][8192]
+    const uint32_t* pass_hi;  // [kNumPrimes][kRootHi]
 };
 
 enum Source : int {
@@ -58,23 +61,30 @@ enum PassMode : int {
     kFused = 2,      // last forward pass of x, pointwise with c-hat, first inverse pass
 };
 
-// One LDS pass of a multi-pass transform over L = 2^logL points.  The array is
-// viewed as L / (R S) blocks of R rows by S contiguous columns (R = 2^r,
-// S = 2^s); the pass transforms along the rows of every column.  A tile holds
-// 2^logN residues: R rows by 2^(logN - r) adjacent columns.  Inside the tile
-// the length-R transform runs as nsteps register steps of radix 2^steps[i].
+// One LDS pass of a multi-pass transform over L points (L = 2^k or 3 * 2^k).
+// The array is viewed as L / (R S) blocks of R rows by S contiguous columns
+// (R = f 2^r with f = 1 or 3, S = 2^s); the pass transforms along the rows of
+// every column.  A tile holds R rows by 2^logC adjacent columns.  Inside the
+// tile the length-R transform runs as register steps: a radix-3 step first when
+// f = 3, then nsteps steps of radix 2^steps[i].
 struct PassArgs {
     uint32_t* data;            // [kNumPrimes][L]
     const uint32_t* other;     // kFused: pre-scaled c-hat, same layout
     const uint32_t* digits;    // kSrcDigits: ceil(n/32) 32-bit digits
-    const uint2* rtw;          // [kNumPrimes][64]: (omega_64^{+-e}, Shoup quotient)
+    const uint2* rtw;          // [kNumPrimes][kRtw]: (omega_64^{+-e}, Shoup quotient),
+                               // then omega_3 and omega_3^2
     uint64_t seed;             // kSrcSeed
     uint64_t n;                // operand bits (sources only)
     uint32_t num_digits;       // ceil(n / 32)
     uint32_t store_limit;      // positions >= this are not stored (L if all)
-    int logL, logN, r, s;
+    uint32_t L;
+    int f, r, s, logC;
     int nsteps;
     int steps[kMaxSteps];
+    // the same as 4-bit fields (step j at bits 4j): radix logs, and the sum of
+    // the logs of the steps before j; read with shifts so that no array of the
+    // kernel argument is ever indexed at run time
+    uint32_t steps_code, above_code;
     int mode, src;
     int scale;                 // multiply the stored output by scale_w (Shoup)
     uint32_t scale_w[kNumPrimes], scale_q[kNumPrimes];
@@ -108,7 +118,6 @@ struct CarryArgs {
 int carry_digits_per_thread(uint32_t num_digits);
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch = 1);
-int pass_threads(int logN, int first_step);
 hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
 hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
 hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);

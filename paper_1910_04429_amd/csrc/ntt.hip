@@ -20,6 +20,11 @@
 // omega_B^o; a strided pass also folds its omega_{RS}^{j k} factor into the
 // bases of its steps, so there is no separate twiddle sweep.
 //
+// Lengths L = 3 * 2^k put the factor 3 in the rows of the first pass, whose
+// first register step is then a radix-3 DFT; all other index arithmetic stays
+// in powers of two.  Twiddle exponents are counted in units of one root of
+// order kOrder = 3 * 2^25, so every length shares one table.
+//
 // Outputs stay in the digit-reversed order that the steps produce; the inverse
 // transform runs the same passes and steps backwards (decimation in time, with
 // inverse roots and pre-multiplication), so no explicit reordering is done:
@@ -108,12 +113,12 @@ __device__ __forceinline__ uint32_t source_digit(const BlockView& a, uint32_t t)
     return v;
 }
 
-// Montgomery form of omega_{2^25}^E, E < 2^25.
+// Montgomery form of w^E for the root w of order kOrder, E < kOrder.
 __device__ __forceinline__ uint32_t root_pow(const Tables& tb, int pi, uint32_t E, uint32_t p,
                                              uint32_t pneg)
 {
     const uint32_t lo = tb.pass_lo[pi * 4096 + (E & 4095u)];
-    const uint32_t hi = tb.pass_hi[pi * 8192 + (E >> 12)];
+    const uint32_t hi = tb.pass_hi[pi * kRootHi + (E >> 12)];
     return fmul_mont(lo, hi, p, pneg);
 }
 
@@ -137,12 +142,13 @@ __device__ __forceinline__ void dif_regs(uint32_t* x, const uint2* __restrict__ 
             for (int j = 0; j < h; ++j) {
                 const uint32_t a = x[i0 + j], b = x[i0 + j + h];
                 x[i0 + j] = fadd(a, b, p);
-                const uint32_t d = fsub(a, b, p);
                 if (j == 0) {
-                    x[i0 + j + h] = d;
+                    x[i0 + j + h] = fsub(a, b, p);
                 } else {
+                    // a - b + p < 2p < 2^32 needs no reduction before Shoup's
+                    // multiply, which takes any 32-bit input
                     const uint2 w = tw[j << (5 - lh)];
-                    x[i0 + j + h] = fmul_shoup(d, w.x, w.y, p);
+                    x[i0 + j + h] = fmul_shoup(a - b + p, w.x, w.y, p);
                 }
             }
         }
@@ -175,16 +181,31 @@ __device__ __forceinline__ void dit_regs(uint32_t* x, const uint2* __restrict__ 
     }
 }
 
-// Geometry of one step inside a tile of R rows x C columns.
+// Geometry of one step inside a tile of R rows x C columns.  Element n of DFT
+// (beta, o, c) sits at row beta B + n sigma + o, column c.  After a forward step
+// output k is multiplied by b^k, b = w^E with
+//   E = o (kOrder / B)                [the inner twiddle omega_B^o, if inner]
+//     + (col0 + c) colmul (kOrder / M)  [the pass twiddle, strided passes]
 struct StepGeo {
     int logC;       // columns
     int logSig;     // row stride of the DFT elements
-    int logB;       // sub-block rows = radix * stride
-    int inner;      // multiply by omega_B^{o k}
-    int colmul;     // multiply by omega_M^{j colmul k} (0: none)
-    int logM;       // pass block length R * S
+    int logB;       // sub-block rows = radix * stride (power-of-two steps)
+    int inner;
+    uint32_t colmul;
+    uint32_t unitB, unitM;
     uint32_t col0;  // global column of tile column 0
 };
+
+__device__ __forceinline__ uint32_t step_exponent(const StepGeo& g, uint32_t o, uint32_t c, bool inv)
+{
+    uint32_t E = g.inner ? o * g.unitB : 0u;
+    if (g.colmul) {
+        E += (g.col0 + c) * g.colmul * g.unitM;
+        if (E >= kOrder) E -= kOrder;
+    }
+    if (inv && E) E = kOrder - E;
+    return E;
+}
 
 // One DIF (forward) or DIT (inverse) step of radix 2^R over every DFT of the tile.
 template <int R, bool kInv>
@@ -196,23 +217,23 @@ __device__ void run_step(uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
     const uint32_t cmask = (1u << g.logC) - 1u;
     const uint32_t omask = (1u << g.logSig) - 1u;
     const bool twiddle = g.inner || g.colmul;
+    // Without the inner twiddle the base depends only on the column, which is
+    // the same for all of a thread's DFTs when the block is a whole number of
+    // rows of columns: compute it once.
+    const bool fixed_base = twiddle && !g.inner && (blockDim.x & cmask) == 0;
+    uint32_t b_fixed = 0;
+    if (fixed_base && (int)threadIdx.x < ndft)
+        b_fixed = root_pow(tb, pi, step_exponent(g, 0u, threadIdx.x & cmask, kInv), p, pneg);
     for (int q = threadIdx.x; q < ndft; q += blockDim.x) {
         const uint32_t c = (uint32_t)q & cmask;
         const uint32_t o = ((uint32_t)q >> g.logC) & omask;
         const uint32_t beta = (uint32_t)q >> (g.logC + g.logSig);
-        // element n of this DFT sits at row beta B + n sigma + o, column c
         const uint32_t base = (((beta << g.logB) + o) << g.logC) + c;
         const uint32_t nstep = 1u << (g.logSig + g.logC);
         uint32_t x[RHO];
-        uint32_t b = 0;  // Montgomery form of the twiddle base
-        if (twiddle) {
-            uint32_t E = 0;
-            if (g.inner) E += o << (kLogMaxLen - g.logB);
-            if (g.colmul) E += ((g.col0 + c) * (uint32_t)g.colmul) << (kLogMaxLen - g.logM);
-            E &= (1u << kLogMaxLen) - 1u;
-            if (kInv) E = (0u - E) & ((1u << kLogMaxLen) - 1u);
-            b = root_pow(tb, pi, E, p, pneg);
-        }
+        uint32_t b = b_fixed;  // Montgomery form of the twiddle base
+        if (twiddle && !fixed_base)
+            b = root_pow(tb, pi, step_exponent(g, o, c, kInv), p, pneg);
         if (!kInv) {
 #pragma unroll
             for (int n = 0; n < RHO; ++n)
@@ -251,6 +272,47 @@ __device__ void run_step(uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
     }
 }
 
+// The radix-3 step that opens a pass whose R rows carry the factor 3: one
+// block of B = R rows, sigma = R / 3.  With w3 a primitive cube root of unity
+// (w3^2 = -1 - w3), the DFT of (x0, x1, x2) is
+//   y0 = x0 + x1 + x2,  y1 = x0 - x2 + v,  y2 = x0 - x1 - v,  v = w3 (x1 - x2);
+// the inverse uses w3^2 in place of w3.  w3p = (w3 or w3^2, Shoup quotient).
+template <bool kInv>
+__device__ void run_step3(uint32_t* sm, int N, const StepGeo& g, uint2 w3p, const Tables& tb,
+                          int pi, uint32_t p, uint32_t pneg)
+{
+    const int ndft = N / 3;
+    const uint32_t cmask = (1u << g.logC) - 1u;
+    const bool twiddle = g.inner || g.colmul;
+    for (int q = threadIdx.x; q < ndft; q += blockDim.x) {
+        const uint32_t c = (uint32_t)q & cmask;
+        const uint32_t o = (uint32_t)q >> g.logC;
+        const uint32_t base = (o << g.logC) + c;
+        const uint32_t nstep = 1u << (g.logSig + g.logC);
+        uint32_t b = 0, b2 = 0;
+        if (twiddle) {
+            b = root_pow(tb, pi, step_exponent(g, o, c, kInv), p, pneg);
+            b2 = fmul_mont(b, b, p, pneg);
+        }
+        uint32_t x0 = sm[swz(base)], x1 = sm[swz(base + nstep)], x2 = sm[swz(base + 2 * nstep)];
+        if (kInv && twiddle) {
+            x1 = fmul_mont(x1, b, p, pneg);
+            x2 = fmul_mont(x2, b2, p, pneg);
+        }
+        const uint32_t v = fmul_shoup(fsub(x1, x2, p), w3p.x, w3p.y, p);
+        uint32_t y0 = fadd(fadd(x0, x1, p), x2, p);
+        uint32_t y1 = fadd(fsub(x0, x2, p), v, p);
+        uint32_t y2 = fsub(fsub(x0, x1, p), v, p);
+        if (!kInv && twiddle) {
+            y1 = fmul_mont(y1, b, p, pneg);
+            y2 = fmul_mont(y2, b2, p, pneg);
+        }
+        sm[swz(base)] = y0;
+        sm[swz(base + nstep)] = y1;
+        sm[swz(base + 2 * nstep)] = y2;
+    }
+}
+
 template <bool kInv>
 __device__ void dispatch_step(int r, uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
                               const Tables& tb, int pi, uint32_t p, uint32_t pneg)
@@ -266,43 +328,73 @@ __device__ void dispatch_step(int r, uint32_t* sm, int N, const StepGeo& g, cons
     }
 }
 
-// Geometry of step s of a pass with the given radix split.
-__device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int logC, int s, uint32_t col0)
+// Geometry of step si of a pass (si counts the radix-3 step, if any, as 0).
+__device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int si, uint32_t col0)
 {
-    int above = 0;
-    for (int i = 0; i < s; ++i) above += a.steps[i];
-    const int logB = a.r - above;
+    const int has3 = a.f == 3;
+    const int total = a.nsteps + has3;
+    const uint32_t M = (uint32_t)a.f << (a.r + a.s);
     StepGeo g;
-    g.logC = logC;
-    g.logB = logB;
-    g.logSig = logB - a.steps[s];
-    g.inner = (s + 1 < a.nsteps);
-    g.logM = a.r + a.s;
+    g.logC = a.logC;
     g.col0 = col0;
-    // the pass factor omega_M^{j k} with k = k_0 + rho_0 (k_1 + rho_1 (k_2 + ...)):
-    // step s takes omega_M^{j rho_0 ... rho_{s-1} k_s}
-    g.colmul = (a.s > 0) ? (1 << above) : 0;
+    g.unitM = kOrder / M;
+    g.inner = si + 1 < total;
+    if (has3 && si == 0) {                    // B = R = 3 2^r, sigma = 2^r
+        g.logB = -1;
+        g.logSig = a.r;
+        g.unitB = kOrder / (3u << a.r);
+        g.colmul = a.s > 0 ? 1u : 0u;
+        return g;
+    }
+    const int j = si - has3;
+    const int above = (int)((a.above_code >> (4 * j)) & 15u);
+    g.logB = a.r - above;
+    g.logSig = g.logB - (int)((a.steps_code >> (4 * j)) & 15u);
+    g.unitB = kOrder >> g.logB;
+    // the pass factor omega_M^{col k} with k = k_0 + rho_0 (k_1 + rho_1 (k_2 + ...)):
+    // step s takes omega_M^{col rho_0 ... rho_{s-1} k_s}
+    g.colmul = a.s > 0 ? ((uint32_t)a.f << above) : 0u;
     return g;
+}
+
+template <bool kInv>
+__device__ void run_pass_steps(const PassArgs& a, uint32_t* sm, int N, uint32_t col0,
+                               const uint2* tw, uint2 w3p, int pi, uint32_t p, uint32_t pneg)
+{
+    const int has3 = a.f == 3;
+    const int total = a.nsteps + has3;
+    for (int k = 0; k < total; ++k) {
+        const int si = kInv ? total - 1 - k : k;
+        const StepGeo g = step_geo(a, si, col0);
+        if (has3 && si == 0)
+            run_step3<kInv>(sm, N, g, w3p, a.tb, pi, p, pneg);
+        else
+            dispatch_step<kInv>((int)((a.steps_code >> (4 * (si - has3))) & 15u), sm, N, g, tw,
+                                a.tb, pi, p, pneg);
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
 {
-    extern __shared__ uint32_t sm[];          // 4 << logN bytes
+    extern __shared__ uint32_t sm[];          // 4 N bytes
     const BlockView bv = block_view(a);
 
     const int pi = blockIdx.y;
     const uint32_t p = kPrimes[pi], pneg = kNegInv[pi];
-    const uint2* twf = a.rtw + pi * 64;       // omega_64^e, e < 32
+    const uint2* twf = a.rtw + pi * kRtw;     // omega_64^e, e < 32
     const uint2* twi = twf + 32;              // omega_64^{-e}
-    uint32_t* data = bv.data + ((size_t)pi << a.logL);
+    const uint2 w3f = twf[64], w3i = twf[65]; // omega_3, omega_3^2
+    uint32_t* data = bv.data + (size_t)pi * a.L;
 
-    const int logN = a.logN;                  // tile residues
-    const int N = 1 << logN;
-    const int logC = logN - a.r;              // columns per tile
+    const int logC = a.logC;                  // columns per tile
+    const uint32_t R = (uint32_t)a.f << a.r;
+    const int N = (int)(R << logC);           // tile residues
+    const uint32_t M = R << a.s;              // pass block length
     const int logCgs = a.s - logC;            // column groups per block
     const uint32_t bg = blockIdx.x >> logCgs;
     const uint32_t col0 = (blockIdx.x & ((1u << logCgs) - 1u)) << logC;
-    const uint32_t blk0 = bg << (a.r + a.s); // global offset of the block
+    const uint32_t blk0 = bg * M;             // global offset of the block
 
     // Tile element (row, c) <-> global position blk0 + row S + col0 + c; moved
     // in groups of 4 consecutive columns (C >= 4) or rows (C == 1).
@@ -332,21 +424,13 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
     __syncthreads();
 
     if (a.mode == kInverse) {
-        for (int s = a.nsteps - 1; s >= 0; --s) {
-            const StepGeo g = step_geo(a, logC, s, col0);
-            dispatch_step<true>(a.steps[s], sm, N, g, twi, a.tb, pi, p, pneg);
-            __syncthreads();
-        }
+        run_pass_steps<true>(a, sm, N, col0, twi, w3i, pi, p, pneg);
     } else {
-        for (int s = 0; s < a.nsteps; ++s) {
-            const StepGeo g = step_geo(a, logC, s, col0);
-            dispatch_step<false>(a.steps[s], sm, N, g, twf, a.tb, pi, p, pneg);
-            __syncthreads();
-        }
+        run_pass_steps<false>(a, sm, N, col0, twf, w3f, pi, p, pneg);
         if (a.mode == kFused) {
             // Pointwise product with the pre-scaled c-hat (same layout), then
             // the inverse of this pass.
-            const uint32_t* other = bv.other + ((size_t)pi << a.logL);
+            const uint32_t* other = bv.other + (size_t)pi * a.L;
             for (int u = threadIdx.x; u < nq; u += blockDim.x) {
                 const uint32_t e = (uint32_t)u << 2;
                 const uint4 cv = *reinterpret_cast<const uint4*>(other + blk0 + e);
@@ -358,11 +442,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
                 *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
             }
             __syncthreads();
-            for (int s = a.nsteps - 1; s >= 0; --s) {
-                const StepGeo g = step_geo(a, logC, s, col0);
-                dispatch_step<true>(a.steps[s], sm, N, g, twi, a.tb, pi, p, pneg);
-                __syncthreads();
-            }
+            run_pass_steps<true>(a, sm, N, col0, twi, w3i, pi, p, pneg);
         }
     }
 
@@ -392,19 +472,16 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
 
 }  // namespace
 
-int pass_threads(int logN, int first_step)
-{
-    // one DFT of the first step per thread, between 1 and 4 waves
-    const int t = 1 << (logN - first_step);
-    return t < 64 ? 64 : (t > kPassThreads ? kPassThreads : t);
-}
-
 hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch)
 {
-    const unsigned tiles = 1u << (a.logL - a.logN);
-    const size_t lds = sizeof(uint32_t) << a.logN;
-    hipLaunchKernelGGL(k_pass, dim3(tiles, kNumPrimes, batch),
-                       dim3(pass_threads(a.logN, a.steps[0])), lds, stream, a);
+    const uint32_t N = ((uint32_t)a.f << a.r) << a.logC;
+    const unsigned tiles = a.L / N;
+    // one DFT of the first step per thread, between 1 and 4 waves
+    const uint32_t first = a.f == 3 ? 3u : (1u << (a.steps_code & 15u));
+    uint32_t threads = N / first;
+    threads = threads < 64 ? 64 : (threads > kPassThreads ? kPassThreads : threads);
+    hipLaunchKernelGGL(k_pass, dim3(tiles, kNumPrimes, batch), dim3(threads),
+                       sizeof(uint32_t) * N, stream, a);
     return hipGetLastError();
 }
 

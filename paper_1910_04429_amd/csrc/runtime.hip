@@ -73,13 +73,31 @@ int fail(pa_ctx* ctx, int code, const char* what, hipError_t e = hipSuccess)
 uint64_t words_of(uint64_t bits) { return (bits + 63) / 64; }
 uint64_t digits_of(uint64_t bits) { return (bits + 31) / 32; }
 
-int log2_len(uint64_t n)
+// Transform length for a block of n bits: the smallest L >= 2D - 1 among 2^l
+// and, for long transforms, 3 * 2^(l-2) (a quarter shorter when it fits, as
+// for n = 10^8: 2D - 1 = 6 249 999 <= 3 * 2^21).
+#ifndef PA_MIXED_RADIX_MIN_LOG
+#define PA_MIXED_RADIX_MIN_LOG 18
+#endif
+// k = l - 2 >= kTileLog + 2 leaves the factor-3 pass at least 2 row bits.
+static_assert(PA_MIXED_RADIX_MIN_LOG >= kTileLog + 4, "factor-3 pass needs a strided head");
+
+struct Len {
+    int f;   // 1 or 3
+    int k;   // L = f 2^k
+    uint64_t L() const { return (uint64_t)f << k; }
+};
+
+Len plan_len(uint64_t n)
 {
-    const uint64_t D = digits_of(n);
+    const uint64_t need = 2 * digits_of(n) - 1;
     int l = 6;
-    while ((1ull << l) < 2 * D - 1) ++l;
-    return l;
+    while ((1ull << l) < need) ++l;
+    if (l >= PA_MIXED_RADIX_MIN_LOG && (3ull << (l - 2)) >= need) return {3, l - 2};
+    return {1, l};
 }
+
+uint64_t len_of(uint64_t n) { return plan_len(n).L(); }
 
 uint32_t chunks_of(uint64_t D)
 {
@@ -128,16 +146,24 @@ int plan_passes(int l, int t, int* r)
 // Register steps of a length-2^r in-tile transform in a tile of 2^t residues:
 // radix up to 64 in big tiles; smaller radices (more, shorter DFTs per step)
 // in small tiles, which have too few threads to hide the latency of long ones.
-int plan_steps(int r, int t, int* st)
+// The contiguous pass splits greedily (its last step has no twiddles, so a
+// small last radix is cheap); strided passes split evenly, since every one of
+// their steps carries twiddles and a lopsided split leaves threads idle.
+int plan_steps(int r, int t, int* st, bool strided)
 {
     const int rmax = t >= 13 ? 6 : (t == 12 ? 5 : 4);
-    int k = 0;
+    const int k = (r + rmax - 1) / rmax;
+    if (strided) {
+        for (int i = 0; i < k; ++i) st[i] = r / k + (i < r % k ? 1 : 0);
+        return k;
+    }
+    int n = 0;
     while (r > rmax) {
-        st[k++] = rmax;
+        st[n++] = rmax;
         r -= rmax;
     }
-    st[k++] = r;
-    return k;
+    st[n++] = r;
+    return n;
 }
 
 void free_workspace(pa_ctx* ctx)
@@ -151,7 +177,7 @@ void free_workspace(pa_ctx* ctx)
 
 int ensure_workspace(pa_ctx* ctx, uint64_t n)
 {
-    const uint64_t L = 1ull << log2_len(n);
+    const uint64_t L = len_of(n);
     const uint64_t D = digits_of(n);
     if (L <= ctx->cap_L && D <= ctx->cap_D)
         return PA_OK;
@@ -226,33 +252,58 @@ struct Recorder {
         if (rec) PA_HIP(ctx, (rec)->end());                                      \
     } while (0)
 
-// Transform plan for L = 2^l: tile size, passes, register steps, output scale.
+// Transform plan for L = f 2^k: tile size, passes, register steps, output scale.
 struct Plan {
-    int l = 0, t = 0, P = 0;
-    int r[8] = {}, s[8] = {};
+    int f = 1, k = 0, t = 0, P = 0;
+    uint64_t L = 0;
+    int r[8] = {}, s[8] = {}, logC[8] = {};
     int nsteps[8] = {};
     int steps[8][kMaxSteps] = {};
     uint32_t scale_w[kNumPrimes] = {}, scale_q[kNumPrimes] = {};
 };
 
-bool make_plan(int l, Plan* pl, unsigned blocks = 1)
+bool make_plan(Len len, Plan* pl, unsigned blocks = 1)
 {
-    pl->l = l;
-    pl->t = plan_tile(l, blocks);
-    pl->P = plan_passes(l, pl->t, pl->r);
-    int rem = l;
+    pl->f = len.f;
+    pl->k = len.k;
+    pl->L = len.L();
+    pl->t = plan_tile(len.k + (len.f == 3 ? 2 : 0), blocks);
+    const int t = pl->t;
+    if (len.f == 1) {
+        pl->P = plan_passes(len.k, t, pl->r);
+    } else {
+        // the first strided pass carries the factor 3: 3 2^r0 rows, tiles of
+        // 3 2^(t-2) residues; the rest of the head as power-of-two passes
+        const int head = len.k - t;
+        if (head < 2) return false;
+        const int r0 = std::min(head, std::min(7, t - 4));
+        pl->r[0] = r0;
+        const int rest = head - r0;
+        int P = 1;
+        if (rest > 0) {
+            const int maxr = (t - 2 < kStridedMaxLog) ? t - 2 : kStridedMaxLog;
+            const int kk = (rest + maxr - 1) / maxr;
+            for (int i = 0; i < kk; ++i) pl->r[P++] = rest / kk + (i < rest % kk ? 1 : 0);
+        }
+        pl->r[P++] = t;
+        pl->P = P;
+    }
+    int rem = len.k;
     for (int i = 0; i < pl->P; ++i) {
-        if (i + 1 < pl->P && pl->t - pl->r[i] < 2) return false;   // strided tiles: >= 4 columns
         rem -= pl->r[i];
         pl->s[i] = rem;
-        pl->nsteps[i] = plan_steps(pl->r[i], pl->t, pl->steps[i]);
+        if (i + 1 < pl->P)
+            pl->logC[i] = (i == 0 && len.f == 3) ? t - 2 - pl->r[i] : t - pl->r[i];
+        else
+            pl->logC[i] = 0;
+        if (i + 1 < pl->P && (pl->logC[i] < 2 || pl->logC[i] > pl->s[i])) return false;
+        pl->nsteps[i] = plan_steps(pl->r[i], t, pl->steps[i], i + 1 < pl->P);
     }
     // c-hat is scaled on its last pass by 2^32 / L so that the Montgomery
     // pointwise product yields x-hat c-hat / L.
-    const uint64_t L = 1ull << l;
     for (int pi = 0; pi < kNumPrimes; ++pi) {
         const uint64_t p = kPrimes[pi];
-        const uint64_t w = ((1ull << 32) % p) * hpow(L % p, p - 2, p) % p;
+        const uint64_t w = ((1ull << 32) % p) * hpow(pl->L % p, p - 2, p) % p;
         pl->scale_w[pi] = (uint32_t)w;
         pl->scale_q[pi] = hshoup(w, p);
     }
@@ -286,7 +337,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
                  Recorder* rec = nullptr)
 {
     const unsigned batch = w.batch;
-    const uint64_t L = 1ull << pl.l;
+    const uint64_t L = pl.L;
     const uint64_t arr = batch * kNumPrimes * 4ull * L;    // residue arrays, all blocks
     const uint64_t outD = kNumPrimes * 4ull * w.digits;    // product coefficients kept
     const int P = pl.P;
@@ -294,17 +345,27 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     PassArgs base{};
     base.num_digits = (uint32_t)digits_of(w.n);
     base.n = w.n;
-    base.logL = pl.l;
-    base.logN = pl.t;
+    base.L = (uint32_t)L;
     base.tb = Tables{ctx->pass_lo, ctx->pass_hi};
     base.rtw = ctx->rtw;
     base.store_limit = (uint32_t)L;
     base.jobs = w.jobs;
     auto geometry = [&](PassArgs& a, int i) {
+        a.f = (i == 0) ? pl.f : 1;
         a.r = pl.r[i];
         a.s = pl.s[i];
+        a.logC = pl.logC[i];
         a.nsteps = pl.nsteps[i];
-        for (int k = 0; k < kMaxSteps; ++k) a.steps[k] = pl.steps[i][k];
+        a.steps_code = a.above_code = 0;
+        int above = 0;
+        for (int k = 0; k < kMaxSteps; ++k) {
+            a.steps[k] = pl.steps[i][k];
+            if (k < pl.nsteps[i]) {
+                a.steps_code |= (uint32_t)pl.steps[i][k] << (4 * k);
+                a.above_code |= (uint32_t)above << (4 * k);
+                above += pl.steps[i][k];
+            }
+        }
     };
     const uint32_t limit = (uint32_t)((digits_of(w.n) + 3) & ~3ull);
 
@@ -405,7 +466,7 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     int rc = ensure_workspace(ctx, n);
     if (rc) return rc;
     Plan pl;
-    if (!make_plan(log2_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    if (!make_plan(plan_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     Work w;
     w.key = reinterpret_cast<const uint32_t*>(d_key);
     w.c = reinterpret_cast<const uint32_t*>(c_words);
@@ -432,13 +493,13 @@ namespace pa {
 
 uint64_t block_workspace_bytes(uint64_t n)
 {
-    const uint64_t L = 1ull << log2_len(n);
+    const uint64_t L = len_of(n);
     return 2 * ((kNumPrimes * 4ull * L + 255) & ~255ull) + ((4ull * status_words(digits_of(n)) + 255) & ~255ull);
 }
 
 void block_layout(uint64_t n, uint8_t* base, BlockBufs* b)
 {
-    const uint64_t L = 1ull << log2_len(n);
+    const uint64_t L = len_of(n);
     const uint64_t arr = (kNumPrimes * 4ull * L + 255) & ~255ull;
     b->A = reinterpret_cast<uint32_t*>(base);
     b->B = reinterpret_cast<uint32_t*>(base + arr);
@@ -448,7 +509,7 @@ void block_layout(uint64_t n, uint8_t* base, BlockBufs* b)
 int enqueue_block(pa_ctx* ctx, const BlockBufs& b, hipStream_t stream)
 {
     Plan pl;
-    if (!make_plan(log2_len(b.n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    if (!make_plan(plan_len(b.n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     Work w;
     w.key = b.key;
     w.c = b.c;
@@ -552,13 +613,13 @@ const char* pa_last_error(const pa_ctx* ctx) { return ctx ? ctx->err : ""; }
 uint64_t pa_transform_length(uint64_t n)
 {
     if (n == 0 || n > PA_MAX_N) return 0;
-    return 1ull << log2_len(n);
+    return len_of(n);
 }
 
 uint64_t pa_workspace_bytes(uint64_t n)
 {
     if (n == 0 || n > PA_MAX_N) return 0;
-    const uint64_t L = 1ull << log2_len(n);
+    const uint64_t L = len_of(n);
     const uint64_t D = digits_of(n);
     return 2 * kNumPrimes * L * 4 + status_words(D) * 4;
 }
@@ -594,44 +655,47 @@ int pa_init(pa_ctx** out, int device)
             rc = PA_EDEVICE;
             break;
         }
-        h_tile = new (std::nothrow) uint2[kNumPrimes * 64];
+        h_tile = new (std::nothrow) uint2[kNumPrimes * kRtw];
         h_lo = new (std::nothrow) uint32_t[kNumPrimes * 4096];
-        h_hi = new (std::nothrow) uint32_t[kNumPrimes * 8192];
+        h_hi = new (std::nothrow) uint32_t[kNumPrimes * kRootHi];
         if (!h_tile || !h_lo || !h_hi) { rc = PA_ENOMEM; break; }
         for (int pi = 0; pi < kNumPrimes; ++pi) {
             const uint64_t p = kPrimes[pi];
             const uint64_t g = generator(p);
-            const uint64_t w25 = hpow(g, (p - 1) >> kLogMaxLen, p);   // order 2^25
-            const uint64_t w6 = hpow(w25, 1ull << (kLogMaxLen - 6), p);     // order 64
+            const uint64_t wo = hpow(g, (p - 1) / kOrder, p);            // order 3 2^25
+            const uint64_t w6 = hpow(wo, kOrder / 64, p);                 // order 64
             const uint64_t w6i = hpow(w6, p - 2, p);
             for (int e = 0; e < 32; ++e) {
                 const uint64_t f = hpow(w6, e, p), b = hpow(w6i, e, p);
-                h_tile[pi * 64 + e] = make_uint2((uint32_t)f, hshoup(f, p));
-                h_tile[pi * 64 + 32 + e] = make_uint2((uint32_t)b, hshoup(b, p));
+                h_tile[pi * kRtw + e] = make_uint2((uint32_t)f, hshoup(f, p));
+                h_tile[pi * kRtw + 32 + e] = make_uint2((uint32_t)b, hshoup(b, p));
             }
+            const uint64_t w3 = hpow(wo, kOrder / 3, p), w3i = w3 * w3 % p;   // cube roots
+            h_tile[pi * kRtw + 64] = make_uint2((uint32_t)w3, hshoup(w3, p));
+            h_tile[pi * kRtw + 65] = make_uint2((uint32_t)w3i, hshoup(w3i, p));
             uint64_t w = 1;
             for (int i = 0; i < 4096; ++i) {
                 h_lo[pi * 4096 + i] = hmont(w, p);
-                w = w * w25 % p;
+                w = w * wo % p;
             }
-            const uint64_t step = hpow(w25, 4096, p);
+            const uint64_t step = hpow(wo, 4096, p);
             w = 1;
-            for (int j = 0; j < 8192; ++j) {
-                h_hi[pi * 8192 + j] = hmont(w, p);
+            for (int j = 0; j < kRootHi; ++j) {
+                h_hi[pi * kRootHi + j] = hmont(w, p);
                 w = w * step % p;
             }
         }
-        if (hipMalloc(&ctx->rtw, sizeof(uint2) * kNumPrimes * 64) != hipSuccess ||
+        if (hipMalloc(&ctx->rtw, sizeof(uint2) * kNumPrimes * kRtw) != hipSuccess ||
             hipMalloc(&ctx->pass_lo, sizeof(uint32_t) * kNumPrimes * 4096) != hipSuccess ||
-            hipMalloc(&ctx->pass_hi, sizeof(uint32_t) * kNumPrimes * 8192) != hipSuccess) {
+            hipMalloc(&ctx->pass_hi, sizeof(uint32_t) * kNumPrimes * kRootHi) != hipSuccess) {
             rc = PA_ENOMEM;
             break;
         }
-        if (hipMemcpy(ctx->rtw, h_tile, sizeof(uint2) * kNumPrimes * 64,
+        if (hipMemcpy(ctx->rtw, h_tile, sizeof(uint2) * kNumPrimes * kRtw,
                       hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(ctx->pass_lo, h_lo, sizeof(uint32_t) * kNumPrimes * 4096,
                       hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(ctx->pass_hi, h_hi, sizeof(uint32_t) * kNumPrimes * 8192,
+            hipMemcpy(ctx->pass_hi, h_hi, sizeof(uint32_t) * kNumPrimes * kRootHi,
                       hipMemcpyHostToDevice) != hipSuccess) {
             rc = PA_EDEVICE;
             break;
@@ -779,13 +843,13 @@ int pa_mul_create(pa_ctx* ctx, uint64_t seed_a, const uint64_t* d_c, uint64_t n,
         if ((w0 & 1) == 0) return fail(ctx, PA_EINVAL, "multiplier c must be odd");
     }
     Plan pl;
-    if (!make_plan(log2_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    if (!make_plan(plan_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     pa_mul* mh = new (std::nothrow) pa_mul;
     if (!mh) return PA_ENOMEM;
     mh->ctx = ctx;
     mh->n = n;
     mh->A = nullptr;
-    const uint64_t L = 1ull << pl.l;
+    const uint64_t L = pl.L;
     hipError_t e = hipMalloc(&mh->A, kNumPrimes * 4ull * L);
     if (e != hipSuccess) {
         delete mh;
@@ -821,7 +885,7 @@ int pa_hash_mul_async(pa_ctx* ctx, const pa_mul* mh, const uint64_t* d_key, uint
     rc = ensure_workspace(ctx, mh->n);
     if (rc) return rc;
     Plan pl;
-    if (!make_plan(log2_len(mh->n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    if (!make_plan(plan_len(mh->n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     const uint64_t n = mh->n;
     Work w;
     w.key = reinterpret_cast<const uint32_t*>(d_key);
@@ -891,7 +955,7 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
     }
     if (ok.empty()) return fail(ctx, PA_EINVAL, "no valid block in the batch");
     std::stable_sort(ok.begin(), ok.end(), [&](size_t a, size_t b) {
-        return log2_len(jobs[a].n) < log2_len(jobs[b].n);
+        return len_of(jobs[a].n) < len_of(jobs[b].n);
     });
     pa_batch* b = new (std::nothrow) pa_batch;
     if (!b) return PA_ENOMEM;
@@ -902,15 +966,15 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
     std::vector<uint64_t> offA(ok.size()), offC(ok.size());
     uint64_t bytes = 0;
     for (size_t i = 0; i < ok.size();) {
-        const int l = log2_len(jobs[ok[i]].n);
+        const uint64_t Lg = len_of(jobs[ok[i]].n);
         size_t e = i;
         uint64_t maxD = 0;
-        while (e < ok.size() && log2_len(jobs[ok[e]].n) == l) {
+        while (e < ok.size() && len_of(jobs[ok[e]].n) == Lg) {
             maxD = std::max<uint64_t>(maxD, digits_of(jobs[ok[e]].n));
             ++e;
         }
         pa_batch::Group g;
-        if (!make_plan(l, &g.plan, (unsigned)(e - i))) {
+        if (!make_plan(plan_len(jobs[ok[i]].n), &g.plan, (unsigned)(e - i))) {
             delete b;
             return fail(ctx, PA_EINVAL, "internal: bad pass plan");
         }
@@ -918,7 +982,7 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
         g.count = (uint32_t)(e - i);
         g.per = carry_digits_per_thread((uint32_t)maxD);
         const uint64_t chunk = (uint64_t)kCarryThreads * g.per;
-        const uint64_t L = 1ull << l;
+        const uint64_t L = Lg;
         for (size_t k = i; k < e; ++k) {
             const pa_job& j = jobs[ok[k]];
             const uint64_t D = digits_of(j.n);
@@ -955,7 +1019,7 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
     }
     b->ws_bytes = bytes;
     for (size_t k = 0; k < h.size(); ++k) {
-        const uint64_t L = 1ull << log2_len(h[k].n);
+        const uint64_t L = len_of(h[k].n);
         h[k].A = reinterpret_cast<uint32_t*>(b->ws + offA[k]);
         h[k].B = reinterpret_cast<uint32_t*>(b->ws + offA[k] + align256(kNumPrimes * 4ull * L));
         h[k].carry = reinterpret_cast<uint32_t*>(b->ws + offC[k]);

@@ -102,10 +102,21 @@ def test_arena_first_fit_and_merge(arena_bin):
 
 
 def test_plan_lengths_cover_the_linear_convolution():
+    """L >= 2D - 1 (no wrap into the low digits), L = 2^k or 3 * 2^k dividing
+    3 * 2^25, and no shorter length of either form would do."""
     import paper_1910_04429_amd as pa
-    for n in [1, 31, 32, 33, 1000, 65_536, 1_000_000, 10**7, 10**8, pa.PA_MAX_N]:
+    order = 3 << 25
+    for n in [1, 31, 32, 33, 1000, 65_536, 1_000_000, 3_145_700, 3_200_000, 10**7, 10**8,
+              pa.PA_MAX_N] + [int(x) for x in np.geomspace(1e5, pa.PA_MAX_N, 40)]:
         L = pa.pa_transform_length(n)
         D = (n + 31) // 32
-        assert L >= 2 * D - 1 and L & (L - 1) == 0 and L <= 1 << 25
-        assert L == 64 or L // 2 < 2 * D - 1
+        need = 2 * D - 1
+        assert L >= need and order % L == 0 and L <= 1 << 25
+        f = 3 if L % 3 == 0 else 1
+        assert (L // f) & (L // f - 1) == 0
+        pow2 = 1 << max(6, (need - 1).bit_length())
+        assert L <= pow2
+        if f == 1 and pow2 >= 1 << 18:
+            assert 3 * pow2 // 4 < need           # the 3 * 2^k length would not fit
         assert pa.pa_workspace_bytes(n) >= 2 * 3 * 4 * L
+    assert pa.pa_transform_length(10**8) == 3 << 21
