@@ -38,6 +38,14 @@ def parse():
                     help="skip the n=1e6, batched and served measurements")
     ap.add_argument("--profile-runs", type=int, default=5)
     ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first stream this many MiB through a plain element-wise kernel "
+                         "(bitwise_not, int64): the known-size reference for HBM counters")
+    ap.add_argument("--ingest-counters", nargs="+", metavar="DIR",
+                    help="no GPU: read rocprofv3 --pmc csv output under these directories "
+                         "(FETCH_SIZE run, WRITE_SIZE run, optional SQ run) and write the "
+                         "per-launch traffic of the NTT pass kernel to " +
+                         os.path.relpath(COUNTERS, ROOT))
     return ap.parse_args()
 
 
@@ -60,6 +68,81 @@ def measured_traffic():
     if c.get("source_hash") != kernel_source_hash():
         return None
     return c.get("bytes_per_launch")
+
+
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9   # CUs x lanes x clock: one wave64 VALU op per CU-cycle
+
+
+def valu_rate(avg_ms):
+    """VALU lane-op rate of the dominant kernel (instructions from the committed
+    SQ counter run x 64 lanes / live launch time), or None."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_hash") != kernel_source_hash() or "SQ_INSTS_VALU" not in c.get("sq", {}):
+        return None
+    ops = c["sq"]["SQ_INSTS_VALU"] * 64 / (avg_ms * 1e-3)
+    return {"lane_ops_per_s": ops, "peak": VALU_PEAK_LANE_OPS,
+            "frac": round(ops / VALU_PEAK_LANE_OPS, 4),
+            "valu_insts_per_launch": c["sq"]["SQ_INSTS_VALU"]}
+
+
+def _counter_rows(d):
+    """(dispatch, kernel name, counter, value) from rocprofv3 csv files under d."""
+    import csv
+    rows = []
+    for dirpath, _, files in os.walk(d):
+        for fn in files:
+            if not fn.endswith("counter_collection.csv"):
+                continue
+            with open(os.path.join(dirpath, fn)) as fh:
+                for r in csv.DictReader(fh):
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"],
+                                 float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"no *counter_collection.csv under {d}")
+    return rows
+
+
+def ingest_counters(dirs, calib_mib, path=COUNTERS):
+    """Per-launch HBM traffic of k_pass from FETCH_SIZE / WRITE_SIZE runs (KiB per
+    dispatch), each scaled by what the same counter reads for the calibration
+    kernel, which reads and writes exactly calib_mib MiB."""
+    known_kib = calib_mib * 1024.0
+    out = {"kernel": "k_pass", "workload": "n1e8", "source_hash": kernel_source_hash(),
+           "calibration": {"kernel": "bitwise_not on int64 (reads and writes the given size)",
+                           "mib": calib_mib}, "sq": {}}
+    per = {}
+    for d in dirs:
+        per_counter = {}
+        for disp, name, counter, val in _counter_rows(d):
+            per_counter.setdefault(counter, {}).setdefault(disp, [name, 0.0])[1] += val
+        for counter, disps in per_counter.items():
+            ntt = [v for _, (nm, v) in sorted(disps.items()) if "k_pass" in nm]
+            cal = [v for _, (nm, v) in sorted(disps.items()) if "bitwise_not" in nm]
+            per[counter] = {"k_pass": ntt, "calib": cal}
+    for counter, key in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        if counter not in per:
+            raise SystemExit(f"{counter} missing from {dirs}")
+        ntt, cal = per[counter]["k_pass"], per[counter]["calib"]
+        if not ntt or not cal:
+            raise SystemExit(f"{counter}: no k_pass or calibration dispatches")
+        factor = known_kib / float(np.median(cal))
+        out["calibration"][f"{key}_kib_read"] = float(np.median(cal))
+        out["calibration"][f"{key}_factor"] = round(factor, 4)
+        out[f"{key}_kib_per_launch"] = float(np.mean(ntt))
+        out[f"{key}_bytes_per_launch"] = float(np.mean(ntt)) * 1024 * factor
+        out[f"{key}_kib_per_pass"] = [float(np.median(ntt[i::5])) for i in range(5)]
+    for counter, v in per.items():
+        if counter.startswith("SQ_") or counter.startswith("GRBM_"):
+            out["sq"][counter] = float(np.mean(v["k_pass"]))
+    out["bytes_per_launch"] = int(out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"])
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+    return out
 
 
 def cpu_baseline(blk, key):
@@ -203,6 +286,10 @@ def main():
               "has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
+    if args.ingest_counters:
+        ingest_counters(args.ingest_counters, args.copy_calibration_mib or 256)
+        return
+
     import torch
     import paper_1910_04429_amd as pa
     import workloads
@@ -210,6 +297,13 @@ def main():
     blk = workloads.single(args.workload)
     key = blk.key()
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        src = torch.zeros(args.copy_calibration_mib << 17, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.bitwise_not(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = pa.pa_init(0)
     t0 = time.perf_counter()
     ms_per_step, d_key, d_out = time_single(pa, ctx, torch, blk, args.steps, args.warmup)
@@ -234,8 +328,10 @@ def main():
     achieved = avg_bytes / (avg_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": f"k_pass ({dom})", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(), "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_bytes_per_launch": int(avg_bytes)}
+                "traffic": measured_traffic() if args.workload == "n1e8" else None,
+                "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": int(avg_bytes),
+                "valu_co_bound": valu_rate(avg_ms) if args.workload == "n1e8" else None}
     breakdown = {k: {"ms_per_step": round(v["ms"] / args.profile_runs, 4),
                      "launches_per_step": v["launches"] // args.profile_runs}
                  for k, v in kinds.items()}

@@ -120,3 +120,33 @@ def test_plan_lengths_cover_the_linear_convolution():
             assert 3 * pow2 // 4 < need           # the 3 * 2^k length would not fit
         assert pa.pa_workspace_bytes(n) >= 2 * 3 * 4 * L
     assert pa.pa_transform_length(10**8) == 3 << 21
+
+
+def _write_counter_csv(d, counter, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w") as f:
+        f.write('"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"\n')
+        for disp, name, val in rows:
+            f.write(f'{disp},"{name}","{counter}",{val}\n')
+
+
+def test_counter_ingest_scales_by_the_calibration_kernel(tmp_path):
+    """bench.py's counter ingest: per-launch k_pass bytes = mean FETCH (KiB) x
+    (known calibration KiB / calibration FETCH) + the same for WRITE."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    calib = "at::native::bitwise_not_kernel"
+    kp = "pa::k_pass(pa::PassArgs)"
+    fetch = [(1, calib, 1024.0)] + [(2 + i, kp, 100.0 * (i % 5 + 1)) for i in range(10)]
+    write = [(1, calib, 4096.0)] + [(2 + i, kp, 50.0) for i in range(10)]
+    _write_counter_csv(tmp_path / "f", "FETCH_SIZE", fetch)
+    _write_counter_csv(tmp_path / "w", "WRITE_SIZE", write)
+    _write_counter_csv(tmp_path / "s", "SQ_INSTS_VALU", [(1, calib, 7.0), (2, kp, 10.0), (3, kp, 30.0)])
+    out = bench.ingest_counters([str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "s")],
+                                4, path=str(tmp_path / "c.json"))
+    # 4 MiB = 4096 KiB known: fetch factor 4, write factor 1
+    assert out["calibration"]["fetch_factor"] == 4.0 and out["calibration"]["write_factor"] == 1.0
+    assert out["fetch_kib_per_pass"] == [100.0, 200.0, 300.0, 400.0, 500.0]
+    assert out["bytes_per_launch"] == int(300.0 * 1024 * 4 + 50.0 * 1024)
+    assert out["sq"]["SQ_INSTS_VALU"] == 20.0
