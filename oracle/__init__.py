@@ -59,6 +59,17 @@ def _load():
                                    ctypes.c_int]
     lib.oracle_collision_count.restype = ctypes.c_int64
     lib.oracle_collision_count.argtypes = [ctypes.c_uint64] * 4
+    lib.oracle_toeplitz_ex.restype = ctypes.c_int
+    lib.oracle_toeplitz_ex.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, _u64p,
+                                       ctypes.c_int]
+    lib.oracle_toeplitz.restype = ctypes.c_int
+    lib.oracle_toeplitz.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                    _u64p, ctypes.c_int]
+    lib.oracle_toeplitz_bits.restype = ctypes.c_int
+    lib.oracle_toeplitz_bits.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, _u64p,
+                                         ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint8)]
+    lib.oracle_toeplitz_collision_count.restype = ctypes.c_int64
+    lib.oracle_toeplitz_collision_count.argtypes = [ctypes.c_uint64] * 4
     _lib = lib
     return lib
 
@@ -145,6 +156,58 @@ def mul_low(a, b, par_levels: int = 0) -> np.ndarray:
 def collision_count(n: int, m: int, x: int, y: int) -> int:
     """delta_G(x, y) of eq. (4) over the whole family G_{c,d} of eq. (6), n <= 20."""
     r = int(_load().oracle_collision_count(n, m, x, y))
+    if r < 0:
+        raise ValueError(f"bad arguments n={n} m={m}")
+    return r
+
+
+# ---------------------------------------------------------------------------
+# Toeplitz-hash variant (toeplitz.c): y = T x over GF(2), T[i][j] = t[i - j + n - 1]
+# ---------------------------------------------------------------------------
+
+def toeplitz_t(seed_t: int, n: int, m: int) -> np.ndarray:
+    """The n + m - 1 bits of t drawn from seed_t."""
+    return expand_operand(seed_t, n + m - 1, False)
+
+
+def _threads(threads):
+    return threads if threads is not None else min(16, os.cpu_count() or 1)
+
+
+def toeplitz_ex(key, t, n: int, m: int, threads: int | None = None) -> np.ndarray:
+    """y = T x for explicit t of n + m - 1 bits."""
+    key, t = _as_words(key, words(n)), _as_words(t, words(n + m - 1))
+    out = np.zeros(words(m), dtype=np.uint64)
+    if _load().oracle_toeplitz_ex(_ptr(key), _ptr(t), n, m, _ptr(out), _threads(threads)) != 0:
+        raise ValueError(f"bad arguments n={n} m={m}")
+    return out
+
+
+def toeplitz(key, seed_t: int, n: int, m: int, threads: int | None = None) -> np.ndarray:
+    """y = T x with t drawn from seed_t."""
+    key = _as_words(key, words(n))
+    out = np.zeros(words(m), dtype=np.uint64)
+    if _load().oracle_toeplitz(_ptr(key), seed_t & (2**64 - 1), n, m, _ptr(out),
+                               _threads(threads)) != 0:
+        raise ValueError(f"bad arguments n={n} m={m}")
+    return out
+
+
+def toeplitz_bits(key, t, n: int, m: int, idx) -> np.ndarray:
+    """Output bits y_i for the positions in idx (uint8 array)."""
+    key, t = _as_words(key, words(n)), _as_words(t, words(n + m - 1))
+    idx = np.ascontiguousarray(idx, dtype=np.uint64)
+    bits = np.zeros(idx.size, dtype=np.uint8)
+    rc = _load().oracle_toeplitz_bits(_ptr(key), _ptr(t), n, m, _ptr(idx), idx.size,
+                                      bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return bits
+
+
+def toeplitz_collision_count(n: int, m: int, x: int, y: int) -> int:
+    """Number of the 2^(n+m-1) Toeplitz matrices with T x = T y (n + m - 1 <= 22)."""
+    r = int(_load().oracle_toeplitz_collision_count(n, m, x, y))
     if r < 0:
         raise ValueError(f"bad arguments n={n} m={m}")
     return r

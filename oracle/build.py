@@ -8,13 +8,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "pa_oracle.c")
+SRCS = [os.path.join(HERE, "pa_oracle.c"), os.path.join(HERE, "toeplitz.c")]
 LIB = os.path.join(HERE, "libpa_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-shared", "-fPIC",
-           "-pthread", SRC, "-o", LIB + ".tmp"]
+           "-pthread", *SRCS, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -57,6 +57,11 @@ def seeds_of(workload_seed: int) -> tuple[int, int, int]:
     return int(s[0]), int(s[1]), int(s[2])
 
 
+def random_words(rng: np.random.Generator, nwords: int) -> np.ndarray:
+    """nwords uniform 64-bit words from a numpy generator (test inputs)."""
+    return rng.integers(0, 2**64, size=nwords, dtype=np.uint64, endpoint=False)
+
+
 @dataclass(frozen=True)
 class Block:
     n: int
