@@ -189,6 +189,25 @@ def host_to_host(pa, ctx, blk, key):
             "note": "pa_hash: key in and result out through pageable host memory"}
 
 
+def toeplitz_rate(pa, ctx, torch, blk, reps):
+    """The Toeplitz-hash variant on the same block (t from seed_a): ms and Mbps."""
+    d_key = torch.from_numpy(blk.key().view(np.int64)).cuda()
+    d_out = torch.zeros(pa.words(blk.m), dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        pa.pa_toeplitz_async(ctx, d_key, None, blk.seed_a, blk.n, blk.m, d_out)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        pa.pa_toeplitz_async(ctx, d_key, None, blk.seed_a, blk.n, blk.m, d_out)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    L, pieces = pa.pa_toeplitz_length(blk.n, blk.m)
+    return {"ms_per_block": round(ms, 4), "mbps": round(blk.n / (ms * 1e-3) / 1e6, 1),
+            "transform_length": L, "key_pieces": pieces}
+
+
 def cached_multiplier(pa, ctx, torch, blk, d_key):
     """Opt-in mode: the multiplier's transform computed once and reused, so a
     block costs two transforms instead of three.  Not the headline value."""
@@ -362,6 +381,11 @@ def main():
                          "paper_mbps_i9": 187.86}
         extra["n1e8_host_to_host"] = host_to_host(pa, ctx, blk, key)
         extra["n1e8_cached_multiplier"] = cached_multiplier(pa, ctx, torch, blk, d_key)
+        extra["toeplitz"] = {
+            "note": "Toeplitz-hash variant (GF(2) Toeplitz matrix, t of n+m-1 bits) on the "
+                    "same transform engine, one element per key bit over one prime",
+            "n1e6": toeplitz_rate(pa, ctx, torch, workloads.single("n1e6"), 50),
+            "n1e8": toeplitz_rate(pa, ctx, torch, blk, 5)}
         extra["batched"] = batched_vs_plain(pa, ctx, torch, workloads)
         extra["served"] = served(pa, torch, workloads, args.served_requests)
 

@@ -258,8 +258,48 @@ int pa_reserve(pa_ctx *ctx, uint64_t n_max);
 /* Device bytes the workspace needs for one block of n bits. */
 uint64_t pa_workspace_bytes(uint64_t n);
 
-/* Transform length used for a block of n bits (a power of two). */
+/* Transform length used for a block of n bits: the smallest 2^k (k >= 6) or
+ * 3 * 2^k (k >= 16) that is >= 2 ceil(n/32) - 1. */
 uint64_t pa_transform_length(uint64_t n);
+
+/*
+ * Toeplitz-hash variant: the family that the paper's Introduction names as the
+ * usual privacy-amplification choice and the alternative to G_{c,d}, computed
+ * on the same transform engine for a same-GPU comparison.  The member for t
+ * (n + m - 1 random bits, the matrix's first column and row) is the m x n
+ * matrix over GF(2) that is constant along its diagonals:
+ *
+ *     T[i][j] = t[i - j + n - 1],     y = T x,
+ *     y_i = XOR_{j < n} (t[i + n - 1 - j] AND x_j),   0 <= i < m,
+ *
+ * i.e. y_i is the parity of coefficient i + n - 1 of the integer convolution
+ * of the bit sequences t and x; the kernels compute that convolution exactly
+ * with one element per bit over one prime, cutting the key into column pieces
+ * when n + m - 1 exceeds the longest transform (3 * 2^25), and XOR the pieces.
+ * Bit layout as above: key ceil(n/64) words, t ceil((n+m-1)/64) words, out
+ * ceil(m/64) words, output bit i is y_i, bits past m in the top word are 0.
+ * A NULL t draws t from seed_t: word i of t is the i-th SplitMix64(seed_t)
+ * output (t is the stream of seed_t masked to n + m - 1 bits).
+ * Sizes: 1 <= m <= n <= PA_MAX_N and m <= PA_TOEPLITZ_MAX_M, else PA_EINVAL.
+ */
+#define PA_TOEPLITZ_MAX_M ((uint64_t)3 << 24)
+
+/* Synchronous: key, t (may be NULL: seeded) and out in host memory. */
+int pa_toeplitz(pa_ctx *ctx, const uint64_t *key, const uint64_t *t, uint64_t seed_t,
+                uint64_t n, uint64_t m, uint64_t *out);
+
+/*
+ * Asynchronous: d_key, d_t (may be NULL: seeded) and d_out are device
+ * pointers; the work is queued on `stream` and the call returns at once.  It
+ * shares the context's workspace with the other entry points, so calls on one
+ * context must be ordered.
+ */
+int pa_toeplitz_async(pa_ctx *ctx, const uint64_t *d_key, const uint64_t *d_t, uint64_t seed_t,
+                      uint64_t n, uint64_t m, uint64_t *d_out, void *stream);
+
+/* Transform length of each piece for a Toeplitz block (0 if the sizes are out
+ * of range); *pieces (may be NULL) receives the number of key pieces. */
+uint64_t pa_toeplitz_length(uint64_t n, uint64_t m, uint64_t *pieces);
 
 #ifdef __cplusplus
 }

@@ -30,6 +30,7 @@ LIB_PATH = os.path.join(_HERE, "libpa.so")
 
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENODEV = 0, 1, 2, 3, 4
 PA_MAX_N = 1 << 29
+PA_TOEPLITZ_MAX_M = 3 << 24
 PA_PROFILE_MAX = 32
 KERNEL_KINDS = {0: "ntt_pass", 1: "carry_local", 2: "carry_scan", 3: "carry_apply"}
 
@@ -107,6 +108,13 @@ _lib.pa_workspace_bytes.restype = _u64
 _lib.pa_workspace_bytes.argtypes = [_u64]
 _lib.pa_transform_length.restype = _u64
 _lib.pa_transform_length.argtypes = [_u64]
+_lib.pa_toeplitz.restype = ctypes.c_int
+_lib.pa_toeplitz.argtypes = [ctypes.c_void_p, _u64p, _u64p, _u64, _u64, _u64, _u64p]
+_lib.pa_toeplitz_async.restype = ctypes.c_int
+_lib.pa_toeplitz_async.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _u64, _u64,
+                                   _u64, ctypes.c_void_p, ctypes.c_void_p]
+_lib.pa_toeplitz_length.restype = _u64
+_lib.pa_toeplitz_length.argtypes = [_u64, _u64, ctypes.POINTER(_u64)]
 _lib.pa_batch_create.restype = ctypes.c_int
 _lib.pa_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Job), ctypes.c_size_t,
                                  ctypes.POINTER(ctypes.c_void_p)]
@@ -278,6 +286,34 @@ def pa_workspace_bytes(n: int) -> int:
 
 def pa_transform_length(n: int) -> int:
     return int(_lib.pa_transform_length(n))
+
+
+def pa_toeplitz(ctx, key, t, seed_t: int, n: int, m: int) -> np.ndarray:
+    """Toeplitz hash y = T x from host memory; t (n + m - 1 bits) or None: seeded."""
+    key = _host_words(key, words(n), "key")
+    tp = None
+    if t is not None:
+        t = _host_words(t, words(n + m - 1), "t")
+        tp = t.ctypes.data_as(_u64p)
+    out = np.zeros(max(words(m), 1), dtype=np.uint64)
+    _check(ctx, _lib.pa_toeplitz(ctx, key.ctypes.data_as(_u64p), tp, seed_t & MASK64, n, m,
+                                 out.ctypes.data_as(_u64p)))
+    return out
+
+
+def pa_toeplitz_async(ctx, d_key, d_t, seed_t: int, n: int, m: int, d_out, stream=None) -> None:
+    """Queue the Toeplitz hash of device tensor d_key into d_out (d_t None: seeded)."""
+    tptr = None if d_t is None else _dev_ptr(d_t, words(n + m - 1), "d_t")
+    _check(ctx, _lib.pa_toeplitz_async(ctx, _dev_ptr(d_key, words(n), "d_key"), tptr,
+                                       seed_t & MASK64, n, m, _dev_ptr(d_out, words(m), "d_out"),
+                                       _stream_handle(stream)))
+
+
+def pa_toeplitz_length(n: int, m: int) -> tuple[int, int]:
+    """(transform length per piece, number of key pieces); (0, 0) when out of range."""
+    pieces = _u64(0)
+    L = int(_lib.pa_toeplitz_length(n, m, ctypes.byref(pieces)))
+    return L, int(pieces.value)
 
 
 def _job_array(jobs):

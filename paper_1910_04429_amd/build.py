@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpa.so")
-SOURCES = ["runtime.hip", "ntt.hip", "carry.hip", "server.hip"]
+SOURCES = ["runtime.hip", "ntt.hip", "carry.hip", "toeplitz.hip", "server.hip"]
 ARCH = "gfx950"
 
 

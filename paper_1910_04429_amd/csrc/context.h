@@ -23,6 +23,9 @@ struct pa_ctx {
     uint64_t* d_c = nullptr;
     uint64_t* d_d = nullptr;
     uint64_t* d_out = nullptr;
+    // the seeded t of the Toeplitz variant
+    uint64_t cap_tbits = 0;
+    uint64_t* tbits = nullptr;
     // side streams (default priority) on which batch groups run concurrently
     static constexpr int kSide = 4;
     hipStream_t side[kSide] = {};

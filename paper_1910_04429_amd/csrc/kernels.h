@@ -30,6 +30,7 @@ enum Source : int {
     kSrcArray = 0,   // residues already in `data`
     kSrcDigits = 1,  // 32-bit digits of an n-bit operand in memory
     kSrcSeed = 2,    // digits of the SplitMix64 stream of `seed`, bit 0 forced to 1
+    kSrcBits = 3,    // element e = bit bit_off + e of `digits` for e < n, else 0
 };
 
 // One block of a batch: where its operands, spectra, carry state and output
@@ -74,7 +75,8 @@ struct PassArgs {
     const uint2* rtw;          // [kNumPrimes][kRtw]: (omega_64^{+-e}, Shoup quotient),
                                // then omega_3 and omega_3^2
     uint64_t seed;             // kSrcSeed
-    uint64_t n;                // operand bits (sources only)
+    uint64_t n;                // operand bits (sources only); kSrcBits: elements
+    uint64_t bit_off;          // kSrcBits: bit of `digits` that element 0 takes
     uint32_t num_digits;       // ceil(n / 32)
     uint32_t store_limit;      // positions >= this are not stored (L if all)
     uint32_t L;
@@ -89,6 +91,7 @@ struct PassArgs {
     int scale;                 // multiply the stored output by scale_w (Shoup)
     uint32_t scale_w[kNumPrimes], scale_q[kNumPrimes];
     Tables tb;
+    int primes;                // primes transformed (grid.y); 0 means all kNumPrimes
     // batch mode (jobs != null): per-block fields come from jobs[blockIdx.z]
     const JobDesc* jobs;
     int role;
@@ -118,6 +121,13 @@ struct CarryArgs {
 int carry_digits_per_thread(uint32_t num_digits);
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch = 1);
+
+// Toeplitz variant: out[j] (or out[j] ^ ..., accumulate) = the 64 bits
+// res[base + 64 j + l] & 1, l < 64, of the first m positions.
+hipError_t launch_parity(const uint32_t* res, uint64_t base, uint64_t m, uint64_t* out,
+                         int accumulate, hipStream_t stream);
+// out[i] = SplitMix64 output i of `seed`, i < words.
+hipError_t launch_stream_words(uint64_t seed, uint64_t words, uint64_t* out, hipStream_t stream);
 hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
 hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
 hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);

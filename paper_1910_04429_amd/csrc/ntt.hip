@@ -61,6 +61,7 @@ struct BlockView {
     const uint32_t* digits;
     uint64_t seed;
     uint64_t n;
+    uint64_t bit_off;
     uint32_t num_digits;
     uint32_t store_limit;
     int src;
@@ -68,7 +69,7 @@ struct BlockView {
 
 __device__ __forceinline__ BlockView block_view(const PassArgs& a)
 {
-    BlockView v{a.data, a.other, a.digits, a.seed, a.n, a.num_digits, a.store_limit, a.src};
+    BlockView v{a.data, a.other, a.digits, a.seed, a.n, a.bit_off, a.num_digits, a.store_limit, a.src};
     if (a.jobs) {
         const JobDesc& j = a.jobs[blockIdx.z];
         v.n = j.n;
@@ -111,6 +112,15 @@ __device__ __forceinline__ uint32_t source_digit(const BlockView& a, uint32_t t)
     if (t == a.num_digits - 1 && top)
         v &= (1u << top) - 1u;
     return v;
+}
+
+// Element t of a bit source: bit bit_off + t of the 32-bit word array, 0 for t >= n.
+__device__ __forceinline__ uint32_t source_bit(const BlockView& a, uint32_t t)
+{
+    if (t >= a.n)
+        return 0;
+    const uint64_t b = a.bit_off + t;
+    return (a.digits[b >> 5] >> (b & 31)) & 1u;
 }
 
 // Montgomery form of w^E for the root w of order kOrder, E < kOrder.
@@ -413,6 +423,11 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
         uint4 v;
         if (bv.src == kSrcArray) {
             v = *reinterpret_cast<const uint4*>(data + pos);
+        } else if (bv.src == kSrcBits) {
+            v.x = source_bit(bv, pos + 0);
+            v.y = source_bit(bv, pos + 1);
+            v.z = source_bit(bv, pos + 2);
+            v.w = source_bit(bv, pos + 3);
         } else {
             v.x = freduce32(source_digit(bv, pos + 0), p);
             v.y = freduce32(source_digit(bv, pos + 1), p);
@@ -480,7 +495,8 @@ hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch)
     const uint32_t first = a.f == 3 ? 3u : (1u << (a.steps_code & 15u));
     uint32_t threads = N / first;
     threads = threads < 64 ? 64 : (threads > kPassThreads ? kPassThreads : threads);
-    hipLaunchKernelGGL(k_pass, dim3(tiles, kNumPrimes, batch), dim3(threads),
+    const unsigned primes = a.primes > 0 && a.primes < kNumPrimes ? (unsigned)a.primes : kNumPrimes;
+    hipLaunchKernelGGL(k_pass, dim3(tiles, primes, batch), dim3(threads),
                        sizeof(uint32_t) * N, stream, a);
     return hipGetLastError();
 }

@@ -88,14 +88,16 @@ struct Len {
     uint64_t L() const { return (uint64_t)f << k; }
 };
 
-Len plan_len(uint64_t n)
+// Smallest transform length >= need (at least 64).
+Len len_for(uint64_t need)
 {
-    const uint64_t need = 2 * digits_of(n) - 1;
     int l = 6;
     while ((1ull << l) < need) ++l;
     if (l >= PA_MIXED_RADIX_MIN_LOG && (3ull << (l - 2)) >= need) return {3, l - 2};
     return {1, l};
 }
+
+Len plan_len(uint64_t n) { return len_for(2 * digits_of(n) - 1); }
 
 uint64_t len_of(uint64_t n) { return plan_len(n).L(); }
 
@@ -175,18 +177,20 @@ void free_workspace(pa_ctx* ctx)
     ctx->cap_L = ctx->cap_D = 0;
 }
 
-int ensure_workspace(pa_ctx* ctx, uint64_t n)
+// Grow the workspace to arrays of kNumPrimes * L residues and the carry state
+// of D digits, keeping any larger capacity it already has.
+int ensure_caps(pa_ctx* ctx, uint64_t L, uint64_t D)
 {
-    const uint64_t L = len_of(n);
-    const uint64_t D = digits_of(n);
     if (L <= ctx->cap_L && D <= ctx->cap_D)
         return PA_OK;
+    L = std::max(L, ctx->cap_L);
+    D = std::max(D, ctx->cap_D);
     PA_HIP(ctx, hipDeviceSynchronize());
     free_workspace(ctx);
     hipError_t e = hipSuccess;
     if ((e = hipMalloc(&ctx->A, kNumPrimes * L * sizeof(uint32_t))) != hipSuccess ||
         (e = hipMalloc(&ctx->B, kNumPrimes * L * sizeof(uint32_t))) != hipSuccess ||
-        (e = hipMalloc(&ctx->status, status_words(D) * sizeof(uint32_t))) != hipSuccess) {
+        (e = hipMalloc(&ctx->status, std::max<uint64_t>(status_words(D), 1) * sizeof(uint32_t))) != hipSuccess) {
         free_workspace(ctx);
         return fail(ctx, PA_ENOMEM, "workspace allocation", e);
     }
@@ -194,6 +198,8 @@ int ensure_workspace(pa_ctx* ctx, uint64_t n)
     ctx->cap_D = D;
     return PA_OK;
 }
+
+int ensure_workspace(pa_ctx* ctx, uint64_t n) { return ensure_caps(ctx, len_of(n), digits_of(n)); }
 
 int ensure_staging(pa_ctx* ctx, uint64_t words, bool operands)
 {
@@ -332,6 +338,26 @@ struct Work {
     bool only_chat = false;            // transform c into A and stop
 };
 
+// Shape of pass i of plan pl in a's geometry fields.
+void pass_geometry(PassArgs& a, const Plan& pl, int i)
+{
+    a.f = (i == 0) ? pl.f : 1;
+    a.r = pl.r[i];
+    a.s = pl.s[i];
+    a.logC = pl.logC[i];
+    a.nsteps = pl.nsteps[i];
+    a.steps_code = a.above_code = 0;
+    int above = 0;
+    for (int k = 0; k < kMaxSteps; ++k) {
+        a.steps[k] = pl.steps[i][k];
+        if (k < pl.nsteps[i]) {
+            a.steps_code |= (uint32_t)pl.steps[i][k] << (4 * k);
+            a.above_code |= (uint32_t)above << (4 * k);
+            above += pl.steps[i][k];
+        }
+    }
+}
+
 // Queue every kernel of the hash (or of one batch group) on `stream`.
 int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
                  Recorder* rec = nullptr)
@@ -350,23 +376,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     base.rtw = ctx->rtw;
     base.store_limit = (uint32_t)L;
     base.jobs = w.jobs;
-    auto geometry = [&](PassArgs& a, int i) {
-        a.f = (i == 0) ? pl.f : 1;
-        a.r = pl.r[i];
-        a.s = pl.s[i];
-        a.logC = pl.logC[i];
-        a.nsteps = pl.nsteps[i];
-        a.steps_code = a.above_code = 0;
-        int above = 0;
-        for (int k = 0; k < kMaxSteps; ++k) {
-            a.steps[k] = pl.steps[i][k];
-            if (k < pl.nsteps[i]) {
-                a.steps_code |= (uint32_t)pl.steps[i][k] << (4 * k);
-                a.above_code |= (uint32_t)above << (4 * k);
-                above += pl.steps[i][k];
-            }
-        }
-    };
+    auto geometry = [&](PassArgs& a, int i) { pass_geometry(a, pl, i); };
     const uint32_t limit = (uint32_t)((digits_of(w.n) + 3) & ~3ull);
 
     for (int i = 0; i < P && !w.have_chat; ++i) {          // c-hat
@@ -594,6 +604,131 @@ int enqueue_batch(pa_batch* b, hipStream_t stream)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Toeplitz variant: y_i = (t * x)[i + n - 1] mod 2 on the transform passes, one
+// element per bit over the first prime.  A block whose linear convolution is
+// longer than the longest transform (kOrder) is cut into column pieces of the
+// key: piece [j0, j0 + w) is itself a Toeplitz product of width w with the t
+// bits [n - j0 - w, n - j0 + m - 1), and the pieces' outputs are XORed.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct ToeplitzPlan {
+    uint64_t pieces = 0, width = 0;
+    Len len{1, 6};
+};
+
+bool toeplitz_plan(uint64_t n, uint64_t m, ToeplitzPlan* tp)
+{
+    const uint64_t lmax = kOrder;
+    if (n == 0 || m == 0 || m > n || n > PA_MAX_N || m > PA_TOEPLITZ_MAX_M) return false;
+    const uint64_t wmax = lmax - m + 1;
+    tp->pieces = (n + wmax - 1) / wmax;
+    tp->width = (n + tp->pieces - 1) / tp->pieces;
+    tp->len = len_for(tp->width + m - 1);
+    return tp->len.L() <= lmax;
+}
+
+int enqueue_toeplitz(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* d_t, uint64_t n,
+                     uint64_t m, uint64_t* d_out, hipStream_t stream)
+{
+    ToeplitzPlan tp;
+    if (!toeplitz_plan(n, m, &tp)) return fail(ctx, PA_EINVAL, "Toeplitz sizes out of range");
+    Plan pl;
+    if (!make_plan(tp.len, &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    const uint64_t L = pl.L;
+    int rc = ensure_caps(ctx, (L + kNumPrimes - 1) / kNumPrimes, 0);
+    if (rc) return rc;
+    const int P = pl.P;
+    PassArgs base{};
+    base.L = (uint32_t)L;
+    base.tb = Tables{ctx->pass_lo, ctx->pass_hi};
+    base.rtw = ctx->rtw;
+    base.store_limit = (uint32_t)L;
+    base.primes = 1;
+    for (uint64_t piece = 0; piece < tp.pieces; ++piece) {
+        const uint64_t j0 = piece * tp.width;
+        const uint64_t w = std::min(tp.width, n - j0);
+        const uint64_t need = w + m - 1;                   // convolution positions used
+        const uint32_t limit = (uint32_t)((need + 3) & ~3ull);
+        for (int i = 0; i < P; ++i) {                      // t-hat into A
+            PassArgs a = base;
+            pass_geometry(a, pl, i);
+            a.data = ctx->A;
+            a.mode = kForward;
+            a.src = kSrcArray;
+            if (i == 0) {
+                a.src = kSrcBits;
+                a.digits = reinterpret_cast<const uint32_t*>(d_t);
+                a.bit_off = n - j0 - w;
+                a.n = need;
+            }
+            if (i == P - 1) {
+                a.scale = 1;
+                a.scale_w[0] = pl.scale_w[0];
+                a.scale_q[0] = pl.scale_q[0];
+            }
+            PA_HIP(ctx, launch_pass(a, stream));
+        }
+        for (int i = 0; i < P; ++i) {                      // x-hat, pointwise, last inverse pass
+            PassArgs a = base;
+            pass_geometry(a, pl, i);
+            a.data = ctx->B;
+            a.other = ctx->A;
+            a.mode = (i == P - 1) ? kFused : kForward;
+            a.src = kSrcArray;
+            if (i == 0) {
+                a.src = kSrcBits;
+                a.digits = reinterpret_cast<const uint32_t*>(d_key);
+                a.bit_off = j0;
+                a.n = w;
+            }
+            if (P == 1) a.store_limit = limit;
+            PA_HIP(ctx, launch_pass(a, stream));
+        }
+        for (int i = P - 2; i >= 0; --i) {                 // remaining inverse passes
+            PassArgs a = base;
+            pass_geometry(a, pl, i);
+            a.data = ctx->B;
+            a.mode = kInverse;
+            a.src = kSrcArray;
+            if (i == 0) a.store_limit = limit;
+            PA_HIP(ctx, launch_pass(a, stream));
+        }
+        PA_HIP(ctx, launch_parity(ctx->B, w - 1, m, d_out, piece > 0, stream));
+    }
+    return PA_OK;
+}
+
+// t drawn from seed_t into the context's buffer.
+int seeded_t(pa_ctx* ctx, uint64_t seed_t, uint64_t bits, hipStream_t stream, const uint64_t** t)
+{
+    const uint64_t w = words_of(bits);
+    if (w > ctx->cap_tbits) {
+        PA_HIP(ctx, hipDeviceSynchronize());
+        (void)hipFree(ctx->tbits);
+        ctx->tbits = nullptr;
+        ctx->cap_tbits = 0;
+        hipError_t e = hipMalloc(&ctx->tbits, w * 8);
+        if (e != hipSuccess) return fail(ctx, PA_ENOMEM, "Toeplitz t allocation", e);
+        ctx->cap_tbits = w;
+    }
+    PA_HIP(ctx, launch_stream_words(seed_t, w, ctx->tbits, stream));
+    *t = ctx->tbits;
+    return PA_OK;
+}
+
+int check_toeplitz(pa_ctx* ctx, uint64_t n, uint64_t m)
+{
+    if (!ctx) return PA_EINVAL;
+    if (n == 0 || m == 0 || m > n) return fail(ctx, PA_EINVAL, "need 1 <= m <= n");
+    if (n > PA_MAX_N) return fail(ctx, PA_EINVAL, "n exceeds PA_MAX_N");
+    if (m > PA_TOEPLITZ_MAX_M) return fail(ctx, PA_EINVAL, "m exceeds PA_TOEPLITZ_MAX_M");
+    return PA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pa_strerror(int status)
@@ -722,6 +857,7 @@ void pa_destroy(pa_ctx* ctx)
     (void)hipFree(ctx->d_out);
     (void)hipFree(ctx->d_c);
     (void)hipFree(ctx->d_d);
+    (void)hipFree(ctx->tbits);
     (void)hipFree(ctx->rtw);
     (void)hipFree(ctx->pass_lo);
     (void)hipFree(ctx->pass_hi);
@@ -1092,6 +1228,63 @@ int pa_hash_many(pa_ctx* ctx, pa_job* jobs, size_t count, void* stream)
     pa_batch_destroy(b);
     if (rc) return rc;
     if (e != hipSuccess) return fail(ctx, PA_EDEVICE, "hipStreamSynchronize", e);
+    return PA_OK;
+}
+
+uint64_t pa_toeplitz_length(uint64_t n, uint64_t m, uint64_t* pieces)
+{
+    ToeplitzPlan tp;
+    if (!toeplitz_plan(n, m, &tp)) {
+        if (pieces) *pieces = 0;
+        return 0;
+    }
+    if (pieces) *pieces = tp.pieces;
+    return tp.len.L();
+}
+
+int pa_toeplitz_async(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* d_t, uint64_t seed_t,
+                      uint64_t n, uint64_t m, uint64_t* d_out, void* stream)
+{
+    int rc = check_toeplitz(ctx, n, m);
+    if (rc) return rc;
+    if (!d_key || !d_out) return fail(ctx, PA_EINVAL, "null key or output pointer");
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    const hipStream_t st = (hipStream_t)stream;
+    if (!d_t) {
+        rc = seeded_t(ctx, seed_t, n + m - 1, st, &d_t);
+        if (rc) return rc;
+    }
+    return enqueue_toeplitz(ctx, d_key, d_t, n, m, d_out, st);
+}
+
+int pa_toeplitz(pa_ctx* ctx, const uint64_t* key, const uint64_t* t, uint64_t seed_t, uint64_t n,
+                uint64_t m, uint64_t* out)
+{
+    int rc = check_toeplitz(ctx, n, m);
+    if (rc) return rc;
+    if (!key || !out) return fail(ctx, PA_EINVAL, "null key or output pointer");
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    const uint64_t tw = words_of(n + m - 1);
+    rc = ensure_staging(ctx, tw, t != nullptr);
+    if (rc) return rc;
+    PA_HIP(ctx, hipMemcpyAsync(ctx->d_key, key, words_of(n) * 8, hipMemcpyHostToDevice,
+                               ctx->stream));
+    const uint64_t* d_t = nullptr;
+    if (t) {
+        PA_HIP(ctx, hipMemcpyAsync(ctx->d_c, t, tw * 8, hipMemcpyHostToDevice, ctx->stream));
+        d_t = ctx->d_c;
+    } else {
+        rc = seeded_t(ctx, seed_t, n + m - 1, ctx->stream, &d_t);
+        if (rc) return rc;
+    }
+    rc = enqueue_toeplitz(ctx, ctx->d_key, d_t, n, m, ctx->d_out, ctx->stream);
+    if (rc) {
+        (void)hipStreamSynchronize(ctx->stream);
+        return rc;
+    }
+    PA_HIP(ctx, hipMemcpyAsync(out, ctx->d_out, words_of(m) * 8, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    PA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PA_OK;
 }
 

@@ -150,3 +150,22 @@ def test_counter_ingest_scales_by_the_calibration_kernel(tmp_path):
     assert out["fetch_kib_per_pass"] == [100.0, 200.0, 300.0, 400.0, 500.0]
     assert out["bytes_per_launch"] == int(300.0 * 1024 * 4 + 50.0 * 1024)
     assert out["sq"]["SQ_INSTS_VALU"] == 20.0
+
+
+def test_toeplitz_plan_covers_the_needed_slice():
+    """Each key piece of width w needs cyclic length L >= w + m - 1 (positions
+    w - 1 .. w + m - 2 of the convolution are then free of wrap-around); L is
+    2^k or 3 * 2^k and at most 3 * 2^25; the pieces cover the key."""
+    import paper_1910_04429_amd as pa
+    for n, m in [(1, 1), (64, 1), (1000, 1000), (10**6, 10**5), (10**7, 2 * 10**6),
+                 (10**8, 4 * 10**7), (60_000_000, 50_000_000), (pa.PA_MAX_N, 1),
+                 (pa.PA_MAX_N, pa.PA_TOEPLITZ_MAX_M)]:
+        L, pieces = pa.pa_toeplitz_length(n, m)
+        width = -(-n // pieces)
+        assert pieces >= 1 and pieces * width >= n and (pieces - 1) * width < n
+        assert width + m - 1 <= L <= 3 << 25
+        f = 3 if L % 3 == 0 else 1
+        assert (L // f) & (L // f - 1) == 0
+    assert pa.pa_toeplitz_length(10**8, 4 * 10**7) == (3 << 25, 2)
+    assert pa.pa_toeplitz_length(10**6, 10**5) == (3 << 19, 1)
+    assert pa.pa_toeplitz_length(5, 6) == (0, 0)

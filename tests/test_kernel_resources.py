@@ -14,7 +14,7 @@ HIPCC = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else shut
 
 
 @pytest.mark.skipif(HIPCC is None, reason="hipcc not available")
-@pytest.mark.parametrize("src", ["ntt.hip", "carry.hip"])
+@pytest.mark.parametrize("src", ["ntt.hip", "carry.hip", "toeplitz.hip"])
 def test_no_scratch_no_vgpr_spill(src, tmp_path):
     cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
            "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"),
