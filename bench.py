@@ -158,7 +158,9 @@ def cpu_baseline(blk, key):
 
 
 def time_single(pa, ctx, torch, blk, steps, warmup):
-    """ms per block for one block through pa_hash_async, key resident."""
+    """ms per block for one block through pa_hash_async, key resident (the
+    context's transform geometry for this length is autotuned first)."""
+    pa.pa_tune(ctx, blk.n, 3)
     d_key = torch.from_numpy(blk.key().view(np.int64)).cuda()
     d_out = torch.zeros(pa.words(blk.m), dtype=torch.int64, device="cuda")
     pa.pa_reserve(ctx, blk.n)
@@ -395,6 +397,8 @@ def main():
         want, cpu = cpu_baseline(blk, key)
         bit_exact = bool(np.array_equal(gpu_out, want))
 
+    plan = pa.pa_plan_get(ctx, blk.n)
+    plan.pop("ms", None)
     pa.pa_destroy(ctx)
     vs = mbps / PAPER_MBPS_N1E8 if args.workload == "n1e8" else None
     line = {
@@ -407,7 +411,8 @@ def main():
         "config": {"workload": f"single PA block {args.workload}: n={blk.n} m={blk.m} "
                                f"uniform random key/c/d from seed "
                                f"{workloads.SINGLE_BLOCKS[args.workload][2]}",
-                   "n": blk.n, "m": blk.m, "transform_length": pa.pa_transform_length(blk.n)},
+                   "n": blk.n, "m": blk.m, "transform_length": pa.pa_transform_length(blk.n),
+                   "plan": plan},
         "bit_exact_vs_oracle": bit_exact,
         "roofline": roofline,
         "kernels": breakdown,

@@ -258,6 +258,45 @@ int pa_reserve(pa_ctx *ctx, uint64_t n_max);
 /* Device bytes the workspace needs for one block of n bits. */
 uint64_t pa_workspace_bytes(uint64_t n);
 
+/*
+ * Transform schedule.  A length-L transform is a few passes over the spectrum:
+ * strided passes, then one contiguous pass whose tiles of 2^tile_log residues
+ * are transformed whole in LDS.  Strided passes use tiles of 2^strided_tile_log
+ * residues; for L = 3 * 2^k the first strided pass has 3 * 2^rows3_log rows
+ * (and tiles of 3 * 2^(strided_tile_log - 2)).  Every geometry gives the same
+ * (exact) result; they differ only in speed.  This is the counterpart of
+ * matching the multiplication method to the operand size, which the paper
+ * leaves to GMP (Sections 2.3 and 3.2.2).
+ */
+typedef struct pa_plan {
+    int tile_log;          /* contiguous pass tile, log2 residues (<= 14) */
+    int strided_tile_log;  /* strided pass tiles, log2 residues (0 with one pass) */
+    int rows3_log;         /* lengths 3 * 2^k: log2 of the factor-3 pass rows / 3; else 0 */
+    int passes;            /* out: passes per transform */
+    float ms;              /* out (pa_tune): one hash of the tuning block with this plan */
+} pa_plan;
+
+/* Valid distinct geometries for blocks of n bits (the default first); writes
+ * up to max, returns the count.  No device needed. */
+int pa_plan_candidates(uint64_t n, pa_plan *out, int max);
+
+/* The geometry ctx uses for blocks of n bits. */
+int pa_plan_get(pa_ctx *ctx, uint64_t n, pa_plan *out);
+
+/* Use geometry *p for every block whose transform length equals that of n
+ * bits (passes and ms are ignored); NULL restores the default.  PA_EINVAL if
+ * the geometry is not valid for that length.  A pa_mul made earlier keeps the
+ * geometry it was made with. */
+int pa_plan_set(pa_ctx *ctx, uint64_t n, const pa_plan *p);
+
+/*
+ * Autotune: time one hash of a seeded n-bit block (m = n / 2) reps times with
+ * every candidate geometry of that transform length on the device, keep the
+ * fastest for ctx (as pa_plan_set would) and return it in *best (may be NULL).
+ * Allocates two temporary device buffers; synchronises the context's stream.
+ */
+int pa_tune(pa_ctx *ctx, uint64_t n, int reps, pa_plan *best);
+
 /* Transform length used for a block of n bits: the smallest 2^k (k >= 6) or
  * 3 * 2^k (k >= 16) that is >= 2 ceil(n/32) - 1. */
 uint64_t pa_transform_length(uint64_t n);

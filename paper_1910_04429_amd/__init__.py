@@ -108,6 +108,19 @@ _lib.pa_workspace_bytes.restype = _u64
 _lib.pa_workspace_bytes.argtypes = [_u64]
 _lib.pa_transform_length.restype = _u64
 _lib.pa_transform_length.argtypes = [_u64]
+class _Plan(ctypes.Structure):
+    _fields_ = [("tile_log", ctypes.c_int), ("strided_tile_log", ctypes.c_int),
+                ("rows3_log", ctypes.c_int), ("passes", ctypes.c_int), ("ms", ctypes.c_float)]
+
+
+_lib.pa_plan_candidates.restype = ctypes.c_int
+_lib.pa_plan_candidates.argtypes = [_u64, ctypes.POINTER(_Plan), ctypes.c_int]
+_lib.pa_plan_get.restype = ctypes.c_int
+_lib.pa_plan_get.argtypes = [ctypes.c_void_p, _u64, ctypes.POINTER(_Plan)]
+_lib.pa_plan_set.restype = ctypes.c_int
+_lib.pa_plan_set.argtypes = [ctypes.c_void_p, _u64, ctypes.POINTER(_Plan)]
+_lib.pa_tune.restype = ctypes.c_int
+_lib.pa_tune.argtypes = [ctypes.c_void_p, _u64, ctypes.c_int, ctypes.POINTER(_Plan)]
 _lib.pa_toeplitz.restype = ctypes.c_int
 _lib.pa_toeplitz.argtypes = [ctypes.c_void_p, _u64p, _u64p, _u64, _u64, _u64, _u64p]
 _lib.pa_toeplitz_async.restype = ctypes.c_int
@@ -286,6 +299,40 @@ def pa_workspace_bytes(n: int) -> int:
 
 def pa_transform_length(n: int) -> int:
     return int(_lib.pa_transform_length(n))
+
+
+def _plan_dict(p) -> dict:
+    return {"tile_log": p.tile_log, "strided_tile_log": p.strided_tile_log,
+            "rows3_log": p.rows3_log, "passes": p.passes, "ms": float(p.ms)}
+
+
+def pa_plan_candidates(n: int, max_count: int = 64) -> list[dict]:
+    """Valid distinct transform geometries for blocks of n bits (default first)."""
+    arr = (_Plan * max_count)()
+    k = int(_lib.pa_plan_candidates(n, arr, max_count))
+    return [_plan_dict(arr[i]) for i in range(k)]
+
+
+def pa_plan_get(ctx, n: int) -> dict:
+    p = _Plan()
+    _check(ctx, _lib.pa_plan_get(ctx, n, ctypes.byref(p)))
+    return _plan_dict(p)
+
+
+def pa_plan_set(ctx, n: int, plan: dict | None) -> None:
+    """Use this geometry for n's transform length (None: the default)."""
+    if plan is None:
+        _check(ctx, _lib.pa_plan_set(ctx, n, None))
+        return
+    p = _Plan(plan["tile_log"], plan.get("strided_tile_log", 0), plan.get("rows3_log", 0), 0, 0.0)
+    _check(ctx, _lib.pa_plan_set(ctx, n, ctypes.byref(p)))
+
+
+def pa_tune(ctx, n: int, reps: int = 3) -> dict:
+    """Time every candidate geometry for n's length on the device; keep the fastest."""
+    p = _Plan()
+    _check(ctx, _lib.pa_tune(ctx, n, reps, ctypes.byref(p)))
+    return _plan_dict(p)
 
 
 def pa_toeplitz(ctx, key, t, seed_t: int, n: int, m: int) -> np.ndarray:

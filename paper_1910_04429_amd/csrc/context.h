@@ -9,7 +9,6 @@ struct pa_ctx {
     int device = 0;
     hipStream_t stream = nullptr;     // used by the synchronous entry points
     // tables
-    uint2* rtw = nullptr;
     uint32_t* pass_lo = nullptr;
     uint32_t* pass_hi = nullptr;
     // workspace, sized for cap_L / cap_D
@@ -26,6 +25,12 @@ struct pa_ctx {
     // the seeded t of the Toeplitz variant
     uint64_t cap_tbits = 0;
     uint64_t* tbits = nullptr;
+    // chosen plan geometry per transform length (slot: k, or 32 + k for 3 2^k);
+    // t == 0: the defaults
+    static constexpr int kPlanSlots = 64;
+    struct PlanChoice {
+        int t = 0, ts = 0, r0 = 0;
+    } plans[kPlanSlots];
     // side streams (default priority) on which batch groups run concurrently
     static constexpr int kSide = 4;
     hipStream_t side[kSide] = {};

@@ -55,6 +55,46 @@ constexpr uint32_t inv_mod(uint64_t a, uint64_t p) { return (uint32_t)pow_mod(a,
 // Montgomery form x 2^32 mod p of a constant.
 constexpr uint32_t to_mont(uint64_t x, uint64_t p) { return (uint32_t)(((x % p) << 32) % p); }
 
+// Smallest generator of the multiplicative group mod the prime p: g with
+// g^((p-1)/q) != 1 for every prime q dividing p - 1 (trial division).
+constexpr uint32_t primitive_root(uint64_t p)
+{
+    uint64_t f[8] = {};
+    int nf = 0;
+    uint64_t q = p - 1;
+    for (uint64_t d = 2; d * d <= q; ++d) {
+        if (q % d == 0) {
+            f[nf++] = d;
+            while (q % d == 0) q /= d;
+        }
+    }
+    if (q > 1) f[nf++] = q;
+    for (uint64_t g = 2; g < p; ++g) {
+        bool ok = true;
+        for (int i = 0; i < nf && ok; ++i)
+            ok = pow_mod(g, (p - 1) / f[i], p) != 1;
+        if (ok) return (uint32_t)g;
+    }
+    return 0;
+}
+
+// The root of unity of order kOrder that every twiddle is a power of.
+constexpr uint32_t order_root(uint64_t p)
+{
+    return (uint32_t)pow_mod(primitive_root(p), (p - 1) / kOrder, p);
+}
+
+constexpr uint32_t kRoot[kNumPrimes] = {order_root(kPrimes[0]), order_root(kPrimes[1]),
+                                        order_root(kPrimes[2])};
+
+static_assert(pow_mod(kRoot[0], kOrder / 2, kPrimes[0]) == kPrimes[0] - 1 &&
+                  pow_mod(kRoot[1], kOrder / 3, kPrimes[1]) != 1 &&
+                  pow_mod(kRoot[2], kOrder, kPrimes[2]) == 1,
+              "root of order 3 * 2^25");
+
+// Shoup quotient floor(w 2^32 / p) of a constant w < p.
+constexpr uint32_t shoup_quotient(uint64_t w, uint64_t p) { return (uint32_t)((w << 32) / p); }
+
 // Garner CRT constants for (p0, p1, p2).
 constexpr uint64_t kP01 = (uint64_t)kPrimes[0] * kPrimes[1];
 constexpr uint32_t kInvP0ModP1M = to_mont(inv_mod(kPrimes[0] % kPrimes[1], kPrimes[1]), kPrimes[1]);

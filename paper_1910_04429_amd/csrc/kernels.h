@@ -16,7 +16,6 @@ constexpr int kMaxSteps = 4;
 constexpr int kPassThreads = 256;
 
 constexpr int kRootHi = (int)(kOrder >> 12);   // 24576 high-table entries
-constexpr int kRtw = 66;                         // small-root table entries per prime
 
 // Device tables shared by every plan, one block per prime.
 struct Tables {
@@ -72,8 +71,6 @@ struct PassArgs {
     uint32_t* data;            // [kNumPrimes][L]
     const uint32_t* other;     // kFused: pre-scaled c-hat, same layout
     const uint32_t* digits;    // kSrcDigits: ceil(n/32) 32-bit digits
-    const uint2* rtw;          // [kNumPrimes][kRtw]: (omega_64^{+-e}, Shoup quotient),
-                               // then omega_3 and omega_3^2
     uint64_t seed;             // kSrcSeed
     uint64_t n;                // operand bits (sources only); kSrcBits: elements
     uint64_t bit_off;          // kSrcBits: bit of `digits` that element 0 takes

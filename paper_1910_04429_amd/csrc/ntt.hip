@@ -13,9 +13,11 @@
 // adjacent columns per tile so that every row segment is a full 128-byte line.
 //
 // Inside a tile the length-R transform is itself split into steps of radix
-// 2^r <= 64.  A step loads each of its small DFTs from LDS into registers, runs
-// the radix-2 butterflies there with the omega_64 powers (uniform across the
-// wavefront), multiplies output k by b^k for a per-DFT base b, and writes back.
+// 2^r <= 32.  A step loads each of its small DFTs from LDS into registers, runs
+// the radix-2 butterflies there with the omega_64 powers (compile-time
+// constants of the prime, so scalar immediates), multiplies output k by b^k
+// for a per-DFT base b, and writes back.  The kernel body is instantiated once
+// per prime and the workgroup picks its prime from blockIdx.y.
 // For DIF step s on sub-blocks of size B split as n = n_s sigma + o the base is
 // omega_B^o; a strided pass also folds its omega_{RS}^{j k} factor into the
 // bases of its steps, so there is no separate twiddle sweep.
@@ -51,6 +53,41 @@ constexpr int bitrev_c(int x, int bits)
         r |= ((x >> i) & 1) << (bits - 1 - i);
     return r;
 }
+
+// Compile-time constants of prime PI: the modulus, -p^{-1} mod 2^32, and the
+// small roots with their Shoup quotients, omega_64^{+-e} (e < 32) and the cube
+// roots of unity, all powers of the order-kOrder root so that they agree with
+// the run-time tables.  Indexed with constants after unrolling, they become
+// scalar immediates instead of registers.
+template <int PI>
+struct PrimeConst {
+    static constexpr uint32_t p = kPrimes[PI];
+    static constexpr uint32_t pneg = kNegInv[PI];
+    static constexpr uint64_t w64 = pow_mod(kRoot[PI], kOrder / 64, kPrimes[PI]);
+    static constexpr uint64_t w64inv = pow_mod(w64, kPrimes[PI] - 2, kPrimes[PI]);
+    static constexpr uint64_t w3 = pow_mod(kRoot[PI], kOrder / 3, kPrimes[PI]);
+    static constexpr uint64_t w3sq = w3 * w3 % kPrimes[PI];
+};
+
+// omega_64^e (kInv: omega_64^{-e}) and its Shoup quotient, e < 32.
+template <int PI, bool kInv>
+struct W64 {
+    struct Table {
+        uint32_t w[32], q[32];
+    };
+    static constexpr Table make()
+    {
+        Table t{};
+        const uint64_t pp = PrimeConst<PI>::p;
+        const uint64_t b = kInv ? PrimeConst<PI>::w64inv : PrimeConst<PI>::w64;
+        for (int e = 0; e < 32; ++e) {
+            t.w[e] = (uint32_t)pow_mod(b, (uint64_t)e, pp);
+            t.q[e] = shoup_quotient(t.w[e], pp);
+        }
+        return t;
+    }
+    static constexpr Table table = make();
+};
 
 // What one workgroup reads and writes: the scalar fields of the pass, or the
 // fields of its block in batch mode.  Kept apart from the kernel argument so
@@ -124,12 +161,12 @@ __device__ __forceinline__ uint32_t source_bit(const BlockView& a, uint32_t t)
 }
 
 // Montgomery form of w^E for the root w of order kOrder, E < kOrder.
-__device__ __forceinline__ uint32_t root_pow(const Tables& tb, int pi, uint32_t E, uint32_t p,
-                                             uint32_t pneg)
+template <int PI>
+__device__ __forceinline__ uint32_t root_pow(const Tables& tb, uint32_t E)
 {
-    const uint32_t lo = tb.pass_lo[pi * 4096 + (E & 4095u)];
-    const uint32_t hi = tb.pass_hi[pi * kRootHi + (E >> 12)];
-    return fmul_mont(lo, hi, p, pneg);
+    const uint32_t lo = tb.pass_lo[PI * 4096 + (E & 4095u)];
+    const uint32_t hi = tb.pass_hi[PI * kRootHi + (E >> 12)];
+    return fmul_mont(lo, hi, PrimeConst<PI>::p, PrimeConst<PI>::pneg);
 }
 
 // LDS index of tile element e: XOR of bits 2..5 with bits 8..11, a bijection
@@ -137,11 +174,13 @@ __device__ __forceinline__ uint32_t root_pow(const Tables& tb, int pi, uint32_t 
 // over the banks.
 __device__ __forceinline__ uint32_t swz(uint32_t e) { return e ^ (((e >> 8) & 15u) << 2); }
 
-// Radix-2^R DIF butterflies in registers: natural input, bit-reversed output.
-// tw[e] = (omega_64^e, Shoup quotient), e < 32.
-template <int R>
-__device__ __forceinline__ void dif_regs(uint32_t* x, const uint2* __restrict__ tw, uint32_t p)
+// Radix-2^R DIF butterflies in registers: natural input, bit-reversed output,
+// with the constant powers of omega_64 of prime PI.
+template <int R, int PI>
+__device__ __forceinline__ void dif_regs(uint32_t* x)
 {
+    constexpr uint32_t p = PrimeConst<PI>::p;
+    constexpr auto& tw = W64<PI, false>::table;
     constexpr int N = 1 << R;
 #pragma unroll
     for (int lh = R - 1; lh >= 0; --lh) {
@@ -157,8 +196,8 @@ __device__ __forceinline__ void dif_regs(uint32_t* x, const uint2* __restrict__ 
                 } else {
                     // a - b + p < 2p < 2^32 needs no reduction before Shoup's
                     // multiply, which takes any 32-bit input
-                    const uint2 w = tw[j << (5 - lh)];
-                    x[i0 + j + h] = fmul_shoup(a - b + p, w.x, w.y, p);
+                    const int e = j << (5 - lh);
+                    x[i0 + j + h] = fmul_shoup(a - b + p, tw.w[e], tw.q[e], p);
                 }
             }
         }
@@ -166,10 +205,12 @@ __device__ __forceinline__ void dif_regs(uint32_t* x, const uint2* __restrict__ 
 }
 
 // Radix-2^R DIT butterflies with inverse roots: bit-reversed input, natural
-// output.  tw[e] = (omega_64^{-e}, Shoup quotient).
-template <int R>
-__device__ __forceinline__ void dit_regs(uint32_t* x, const uint2* __restrict__ tw, uint32_t p)
+// output.
+template <int R, int PI>
+__device__ __forceinline__ void dit_regs(uint32_t* x)
 {
+    constexpr uint32_t p = PrimeConst<PI>::p;
+    constexpr auto& tw = W64<PI, true>::table;
     constexpr int N = 1 << R;
 #pragma unroll
     for (int lh = 0; lh < R; ++lh) {
@@ -181,8 +222,8 @@ __device__ __forceinline__ void dit_regs(uint32_t* x, const uint2* __restrict__ 
                 const uint32_t a = x[i0 + j];
                 uint32_t b = x[i0 + j + h];
                 if (j != 0) {
-                    const uint2 w = tw[j << (5 - lh)];
-                    b = fmul_shoup(b, w.x, w.y, p);
+                    const int e = j << (5 - lh);
+                    b = fmul_shoup(b, tw.w[e], tw.q[e], p);
                 }
                 x[i0 + j] = fadd(a, b, p);
                 x[i0 + j + h] = fsub(a, b, p);
@@ -218,10 +259,10 @@ __device__ __forceinline__ uint32_t step_exponent(const StepGeo& g, uint32_t o, 
 }
 
 // One DIF (forward) or DIT (inverse) step of radix 2^R over every DFT of the tile.
-template <int R, bool kInv>
-__device__ void run_step(uint32_t* sm, int N, const StepGeo& g, const uint2* tw, const Tables& tb,
-                         int pi, uint32_t p, uint32_t pneg)
+template <int R, bool kInv, int PI>
+__device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, const Tables& tb)
 {
+    constexpr uint32_t p = PrimeConst<PI>::p, pneg = PrimeConst<PI>::pneg;
     constexpr int RHO = 1 << R;
     const int ndft = N >> R;
     const uint32_t cmask = (1u << g.logC) - 1u;
@@ -233,7 +274,7 @@ __device__ void run_step(uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
     const bool fixed_base = twiddle && !g.inner && (blockDim.x & cmask) == 0;
     uint32_t b_fixed = 0;
     if (fixed_base && (int)threadIdx.x < ndft)
-        b_fixed = root_pow(tb, pi, step_exponent(g, 0u, threadIdx.x & cmask, kInv), p, pneg);
+        b_fixed = root_pow<PI>(tb, step_exponent(g, 0u, threadIdx.x & cmask, kInv));
     for (int q = threadIdx.x; q < ndft; q += blockDim.x) {
         const uint32_t c = (uint32_t)q & cmask;
         const uint32_t o = ((uint32_t)q >> g.logC) & omask;
@@ -243,12 +284,12 @@ __device__ void run_step(uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
         uint32_t x[RHO];
         uint32_t b = b_fixed;  // Montgomery form of the twiddle base
         if (twiddle && !fixed_base)
-            b = root_pow(tb, pi, step_exponent(g, o, c, kInv), p, pneg);
+            b = root_pow<PI>(tb, step_exponent(g, o, c, kInv));
         if (!kInv) {
 #pragma unroll
             for (int n = 0; n < RHO; ++n)
                 x[n] = sm[swz(base + n * nstep)];
-            dif_regs<R>(x, tw, p);
+            dif_regs<R, PI>(x);
             if (twiddle) {
                 uint32_t w = b;
 #pragma unroll
@@ -274,7 +315,7 @@ __device__ void run_step(uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
                     if (k + 1 < RHO) w = fmul_mont(w, b, p, pneg);
                 }
             }
-            dit_regs<R>(x, tw, p);
+            dit_regs<R, PI>(x);
 #pragma unroll
             for (int n = 0; n < RHO; ++n)
                 sm[swz(base + n * nstep)] = x[n];
@@ -287,10 +328,12 @@ __device__ void run_step(uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
 // (w3^2 = -1 - w3), the DFT of (x0, x1, x2) is
 //   y0 = x0 + x1 + x2,  y1 = x0 - x2 + v,  y2 = x0 - x1 - v,  v = w3 (x1 - x2);
 // the inverse uses w3^2 in place of w3.  w3p = (w3 or w3^2, Shoup quotient).
-template <bool kInv>
-__device__ void run_step3(uint32_t* sm, int N, const StepGeo& g, uint2 w3p, const Tables& tb,
-                          int pi, uint32_t p, uint32_t pneg)
+template <bool kInv, int PI>
+__device__ __forceinline__ void run_step3(uint32_t* sm, int N, const StepGeo& g, const Tables& tb)
 {
+    constexpr uint32_t p = PrimeConst<PI>::p, pneg = PrimeConst<PI>::pneg;
+    constexpr uint32_t w3 = (uint32_t)(kInv ? PrimeConst<PI>::w3sq : PrimeConst<PI>::w3);
+    constexpr uint32_t w3q = shoup_quotient(w3, PrimeConst<PI>::p);
     const int ndft = N / 3;
     const uint32_t cmask = (1u << g.logC) - 1u;
     const bool twiddle = g.inner || g.colmul;
@@ -301,7 +344,7 @@ __device__ void run_step3(uint32_t* sm, int N, const StepGeo& g, uint2 w3p, cons
         const uint32_t nstep = 1u << (g.logSig + g.logC);
         uint32_t b = 0, b2 = 0;
         if (twiddle) {
-            b = root_pow(tb, pi, step_exponent(g, o, c, kInv), p, pneg);
+            b = root_pow<PI>(tb, step_exponent(g, o, c, kInv));
             b2 = fmul_mont(b, b, p, pneg);
         }
         uint32_t x0 = sm[swz(base)], x1 = sm[swz(base + nstep)], x2 = sm[swz(base + 2 * nstep)];
@@ -309,7 +352,7 @@ __device__ void run_step3(uint32_t* sm, int N, const StepGeo& g, uint2 w3p, cons
             x1 = fmul_mont(x1, b, p, pneg);
             x2 = fmul_mont(x2, b2, p, pneg);
         }
-        const uint32_t v = fmul_shoup(fsub(x1, x2, p), w3p.x, w3p.y, p);
+        const uint32_t v = fmul_shoup(x1 - x2 + p, w3, w3q, p);
         uint32_t y0 = fadd(fadd(x0, x1, p), x2, p);
         uint32_t y1 = fadd(fsub(x0, x2, p), v, p);
         uint32_t y2 = fsub(fsub(x0, x1, p), v, p);
@@ -323,17 +366,15 @@ __device__ void run_step3(uint32_t* sm, int N, const StepGeo& g, uint2 w3p, cons
     }
 }
 
-template <bool kInv>
-__device__ void dispatch_step(int r, uint32_t* sm, int N, const StepGeo& g, const uint2* tw,
-                              const Tables& tb, int pi, uint32_t p, uint32_t pneg)
+template <bool kInv, int PI>
+__device__ __forceinline__ void dispatch_step(int r, uint32_t* sm, int N, const StepGeo& g, const Tables& tb)
 {
     switch (r) {
-    case 1: run_step<1, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
-    case 2: run_step<2, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
-    case 3: run_step<3, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
-    case 4: run_step<4, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
-    case 5: run_step<5, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
-    case 6: run_step<6, kInv>(sm, N, g, tw, tb, pi, p, pneg); break;
+    case 1: run_step<1, kInv, PI>(sm, N, g, tb); break;
+    case 2: run_step<2, kInv, PI>(sm, N, g, tb); break;
+    case 3: run_step<3, kInv, PI>(sm, N, g, tb); break;
+    case 4: run_step<4, kInv, PI>(sm, N, g, tb); break;
+    case 5: run_step<5, kInv, PI>(sm, N, g, tb); break;
     default: break;
     }
 }
@@ -367,9 +408,8 @@ __device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int si, uint32_t 
     return g;
 }
 
-template <bool kInv>
-__device__ void run_pass_steps(const PassArgs& a, uint32_t* sm, int N, uint32_t col0,
-                               const uint2* tw, uint2 w3p, int pi, uint32_t p, uint32_t pneg)
+template <bool kInv, int PI>
+__device__ __forceinline__ void run_pass_steps(const PassArgs& a, uint32_t* sm, int N, uint32_t col0)
 {
     const int has3 = a.f == 3;
     const int total = a.nsteps + has3;
@@ -377,25 +417,21 @@ __device__ void run_pass_steps(const PassArgs& a, uint32_t* sm, int N, uint32_t 
         const int si = kInv ? total - 1 - k : k;
         const StepGeo g = step_geo(a, si, col0);
         if (has3 && si == 0)
-            run_step3<kInv>(sm, N, g, w3p, a.tb, pi, p, pneg);
+            run_step3<kInv, PI>(sm, N, g, a.tb);
         else
-            dispatch_step<kInv>((int)((a.steps_code >> (4 * (si - has3))) & 15u), sm, N, g, tw,
-                                a.tb, pi, p, pneg);
+            dispatch_step<kInv, PI>((int)((a.steps_code >> (4 * (si - has3))) & 15u), sm, N, g,
+                                    a.tb);
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
+// One pass over the tile of prime PI owned by this workgroup.
+template <int PI>
+__device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
 {
-    extern __shared__ uint32_t sm[];          // 4 N bytes
+    constexpr uint32_t p = PrimeConst<PI>::p, pneg = PrimeConst<PI>::pneg;
     const BlockView bv = block_view(a);
-
-    const int pi = blockIdx.y;
-    const uint32_t p = kPrimes[pi], pneg = kNegInv[pi];
-    const uint2* twf = a.rtw + pi * kRtw;     // omega_64^e, e < 32
-    const uint2* twi = twf + 32;              // omega_64^{-e}
-    const uint2 w3f = twf[64], w3i = twf[65]; // omega_3, omega_3^2
-    uint32_t* data = bv.data + (size_t)pi * a.L;
+    uint32_t* data = bv.data + (size_t)PI * a.L;
 
     const int logC = a.logC;                  // columns per tile
     const uint32_t R = (uint32_t)a.f << a.r;
@@ -439,13 +475,13 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
     __syncthreads();
 
     if (a.mode == kInverse) {
-        run_pass_steps<true>(a, sm, N, col0, twi, w3i, pi, p, pneg);
+        run_pass_steps<true, PI>(a, sm, N, col0);
     } else {
-        run_pass_steps<false>(a, sm, N, col0, twf, w3f, pi, p, pneg);
+        run_pass_steps<false, PI>(a, sm, N, col0);
         if (a.mode == kFused) {
             // Pointwise product with the pre-scaled c-hat (same layout), then
             // the inverse of this pass.
-            const uint32_t* other = bv.other + (size_t)pi * a.L;
+            const uint32_t* other = bv.other + (size_t)PI * a.L;
             for (int u = threadIdx.x; u < nq; u += blockDim.x) {
                 const uint32_t e = (uint32_t)u << 2;
                 const uint4 cv = *reinterpret_cast<const uint4*>(other + blk0 + e);
@@ -457,7 +493,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
                 *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
             }
             __syncthreads();
-            run_pass_steps<true>(a, sm, N, col0, twi, w3i, pi, p, pneg);
+            run_pass_steps<true, PI>(a, sm, N, col0);
         }
     }
 
@@ -474,7 +510,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
         }
         uint4 v = *reinterpret_cast<const uint4*>(&sm[swz(e)]);
         if (a.scale) {
-            const uint32_t w = a.scale_w[pi], q = a.scale_q[pi];
+            const uint32_t w = a.scale_w[PI], q = a.scale_q[PI];
             v.x = fmul_shoup(v.x, w, q, p);
             v.y = fmul_shoup(v.y, w, q, p);
             v.z = fmul_shoup(v.z, w, q, p);
@@ -482,6 +518,16 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
         }
         if (pos < bv.store_limit)
             *reinterpret_cast<uint4*>(data + pos) = v;
+    }
+}
+
+__global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
+{
+    extern __shared__ uint32_t sm[];          // 4 N bytes
+    switch (blockIdx.y) {
+    case 0: pass_tile<0>(a, sm); break;
+    case 1: pass_tile<1>(a, sm); break;
+    default: pass_tile<2>(a, sm); break;
     }
 }
 

@@ -28,28 +28,6 @@ uint64_t hpow(uint64_t b, uint64_t e, uint64_t p)
     return r;
 }
 
-// Smallest generator of the multiplicative group mod prime p.
-uint64_t generator(uint64_t p)
-{
-    uint64_t f[16];
-    int nf = 0;
-    uint64_t q = p - 1;
-    for (uint64_t d = 2; d * d <= q; ++d) {
-        if (q % d == 0) {
-            f[nf++] = d;
-            while (q % d == 0) q /= d;
-        }
-    }
-    if (q > 1) f[nf++] = q;
-    for (uint64_t g = 2; g < p; ++g) {
-        bool ok = true;
-        for (int i = 0; i < nf && ok; ++i)
-            ok = hpow(g, (p - 1) / f[i], p) != 1;
-        if (ok) return g;
-    }
-    return 0;
-}
-
 uint32_t hmont(uint64_t x, uint64_t p) { return (uint32_t)(((x % p) << 32) % p); }
 uint32_t hshoup(uint64_t w, uint64_t p) { return (uint32_t)((w << 32) / p); }
 
@@ -111,33 +89,35 @@ uint32_t chunks_of(uint64_t D)
 uint64_t status_words(uint64_t D) { return 2 * ((D + kCarryThreads * 4 - 1) / (kCarryThreads * 4)); }
 
 #ifndef PA_TILE_SLACK
-#define PA_TILE_SLACK 6
+#define PA_TILE_SLACK 8
 #endif
+constexpr int kTileDefaultLog = 13;
 
-// Tile size (log2 residues) for a length-2^l transform run for `blocks`
-// blocks at once: whole 2^14 tiles when there is parallelism to spare (a
-// batch, or a long transform); for a lone short transform, smaller tiles so
-// that there are enough workgroups to spread over the chip.
+// Default contiguous tile (log2 residues) for a transform of about 2^l
+// residues run for `blocks` blocks at once.  Tiles of 2^13 (32 KB of LDS) let
+// five workgroups share a CU, against two for 2^14, which keeps the last wave
+// of workgroups short; a lone short transform takes smaller tiles so that it
+// still spreads over the chip.  pa_tune measures instead of guessing.
 int plan_tile(int l, unsigned blocks = 1)
 {
     if (l <= kTileMinLog) return l;
     int t = blocks >= 16 ? l : l - PA_TILE_SLACK;
     if (t < kTileMinLog) t = kTileMinLog;
-    if (t > kTileLog) t = kTileLog;
+    if (t > kTileDefaultLog) t = kTileDefaultLog;
     return t;
 }
 
-// Passes of a length-2^l transform with tiles of 2^t: strided passes of at
-// most 2^9 rows (and at least 4 columns per tile), then one contiguous pass
-// over whole tiles.
-int plan_passes(int l, int t, int* r)
+// Passes of a length-2^l transform: strided passes of at most 2^9 rows (each
+// tile 2^ts residues, at least 4 columns), then one contiguous pass over whole
+// tiles of 2^t.
+int plan_passes(int l, int t, int ts, int* r)
 {
     if (l <= t) {
         r[0] = l;
         return 1;
     }
     const int head = l - t;
-    const int maxr = (t - 2 < kStridedMaxLog) ? t - 2 : kStridedMaxLog;
+    const int maxr = (ts - 2 < kStridedMaxLog) ? ts - 2 : kStridedMaxLog;
     const int k = (head + maxr - 1) / maxr;
     for (int i = 0; i < k; ++i)
         r[i] = head / k + (i < head % k ? 1 : 0);
@@ -146,14 +126,16 @@ int plan_passes(int l, int t, int* r)
 }
 
 // Register steps of a length-2^r in-tile transform in a tile of 2^t residues:
-// radix up to 64 in big tiles; smaller radices (more, shorter DFTs per step)
-// in small tiles, which have too few threads to hide the latency of long ones.
+// radix up to 32 in big tiles (a radix-64 step needs 64 twiddle constants in
+// scalar registers and twice the vector registers); smaller radices (more,
+// shorter DFTs per step) in small tiles, which have too few threads to hide
+// the latency of long ones.
 // The contiguous pass splits greedily (its last step has no twiddles, so a
 // small last radix is cheap); strided passes split evenly, since every one of
 // their steps carries twiddles and a lopsided split leaves threads idle.
 int plan_steps(int r, int t, int* st, bool strided)
 {
-    const int rmax = t >= 13 ? 6 : (t == 12 ? 5 : 4);
+    const int rmax = t >= 12 ? 5 : 4;
     const int k = (r + rmax - 1) / rmax;
     if (strided) {
         for (int i = 0; i < k; ++i) st[i] = r / k + (i < r % k ? 1 : 0);
@@ -260,7 +242,7 @@ struct Recorder {
 
 // Transform plan for L = f 2^k: tile size, passes, register steps, output scale.
 struct Plan {
-    int f = 1, k = 0, t = 0, P = 0;
+    int f = 1, k = 0, t = 0, ts = 0, P = 0;
     uint64_t L = 0;
     int r[8] = {}, s[8] = {}, logC[8] = {};
     int nsteps[8] = {};
@@ -268,42 +250,58 @@ struct Plan {
     uint32_t scale_w[kNumPrimes] = {}, scale_q[kNumPrimes] = {};
 };
 
-bool make_plan(Len len, Plan* pl, unsigned blocks = 1)
+// Plan geometry: contiguous tile 2^t, strided tiles 2^ts (3 2^(ts-2) for the
+// factor-3 pass, which has 3 2^r0 rows).  Zero fields take the defaults.
+struct PlanParams {
+    int t = 0, ts = 0, r0 = 0;
+};
+
+bool make_plan(Len len, Plan* pl, unsigned blocks = 1, PlanParams pp = {})
 {
     pl->f = len.f;
     pl->k = len.k;
     pl->L = len.L();
-    pl->t = plan_tile(len.k + (len.f == 3 ? 2 : 0), blocks);
-    const int t = pl->t;
+    const int t = pp.t ? pp.t : plan_tile(len.k + (len.f == 3 ? 2 : 0), blocks);
+    // strided tiles: the full 64 KB for the factor-3 pass of long transforms
+    // (3 2^8 rows of 16 columns at 2^13 contiguous tiles), else as contiguous
+    const int ts = pp.ts ? pp.ts : ((len.f == 3 && t >= kTileDefaultLog) ? kTileLog : t);
+    if (t > kTileLog || ts > kTileLog || ts < 6 || t < 1) return false;
+    pl->t = t;
+    pl->ts = ts;
     if (len.f == 1) {
-        pl->P = plan_passes(len.k, t, pl->r);
+        pl->P = plan_passes(len.k, t, ts, pl->r);
     } else {
         // the first strided pass carries the factor 3: 3 2^r0 rows, tiles of
-        // 3 2^(t-2) residues; the rest of the head as power-of-two passes
+        // 3 2^(ts-2) residues; the rest of the head as power-of-two passes
         const int head = len.k - t;
         if (head < 2) return false;
-        const int r0 = std::min(head, std::min(7, t - 4));
+        const int r0 = pp.r0 ? pp.r0 : std::min(head, std::min(kStridedMaxLog, ts - 4));
+        if (r0 < 2 || r0 > head || r0 > kStridedMaxLog) return false;
         pl->r[0] = r0;
         const int rest = head - r0;
         int P = 1;
         if (rest > 0) {
-            const int maxr = (t - 2 < kStridedMaxLog) ? t - 2 : kStridedMaxLog;
+            const int maxr = (ts - 2 < kStridedMaxLog) ? ts - 2 : kStridedMaxLog;
             const int kk = (rest + maxr - 1) / maxr;
+            if (kk + 2 > 8) return false;
             for (int i = 0; i < kk; ++i) pl->r[P++] = rest / kk + (i < rest % kk ? 1 : 0);
         }
         pl->r[P++] = t;
         pl->P = P;
     }
+    if (pl->P > 8) return false;
     int rem = len.k;
     for (int i = 0; i < pl->P; ++i) {
         rem -= pl->r[i];
         pl->s[i] = rem;
-        if (i + 1 < pl->P)
-            pl->logC[i] = (i == 0 && len.f == 3) ? t - 2 - pl->r[i] : t - pl->r[i];
+        const bool strided = i + 1 < pl->P;
+        if (strided)
+            pl->logC[i] = (i == 0 && len.f == 3) ? ts - 2 - pl->r[i] : ts - pl->r[i];
         else
             pl->logC[i] = 0;
-        if (i + 1 < pl->P && (pl->logC[i] < 2 || pl->logC[i] > pl->s[i])) return false;
-        pl->nsteps[i] = plan_steps(pl->r[i], t, pl->steps[i], i + 1 < pl->P);
+        if (strided && (pl->logC[i] < 2 || pl->logC[i] > pl->s[i])) return false;
+        pl->nsteps[i] = plan_steps(pl->r[i], strided ? ts : t, pl->steps[i], strided);
+        if (pl->nsteps[i] > kMaxSteps) return false;
     }
     // c-hat is scaled on its last pass by 2^32 / L so that the Montgomery
     // pointwise product yields x-hat c-hat / L.
@@ -314,6 +312,21 @@ bool make_plan(Len len, Plan* pl, unsigned blocks = 1)
         pl->scale_q[pi] = hshoup(w, p);
     }
     return true;
+}
+
+// Index of a transform length in the context's table of chosen plans.
+int len_slot(Len len) { return (len.f == 3 ? 32 : 0) + len.k; }
+
+// The plan a context uses for length len: its tuned or set geometry, else the
+// defaults.
+bool plan_for(const pa_ctx* ctx, Len len, Plan* pl)
+{
+    const int i = len_slot(len);
+    if (ctx && i < pa_ctx::kPlanSlots && ctx->plans[i].t) {
+        const PlanParams pp{ctx->plans[i].t, ctx->plans[i].ts, ctx->plans[i].r0};
+        if (make_plan(len, pl, 1, pp)) return true;
+    }
+    return make_plan(len, pl);
 }
 
 // Operands of one block.  In batch mode the kernels read them from the job
@@ -373,7 +386,6 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     base.n = w.n;
     base.L = (uint32_t)L;
     base.tb = Tables{ctx->pass_lo, ctx->pass_hi};
-    base.rtw = ctx->rtw;
     base.store_limit = (uint32_t)L;
     base.jobs = w.jobs;
     auto geometry = [&](PassArgs& a, int i) { pass_geometry(a, pl, i); };
@@ -476,7 +488,7 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     int rc = ensure_workspace(ctx, n);
     if (rc) return rc;
     Plan pl;
-    if (!make_plan(plan_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    if (!plan_for(ctx, plan_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     Work w;
     w.key = reinterpret_cast<const uint32_t*>(d_key);
     w.c = reinterpret_cast<const uint32_t*>(c_words);
@@ -519,7 +531,7 @@ void block_layout(uint64_t n, uint8_t* base, BlockBufs* b)
 int enqueue_block(pa_ctx* ctx, const BlockBufs& b, hipStream_t stream)
 {
     Plan pl;
-    if (!make_plan(plan_len(b.n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    if (!plan_for(ctx, plan_len(b.n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     Work w;
     w.key = b.key;
     w.c = b.c;
@@ -635,7 +647,7 @@ int enqueue_toeplitz(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* d_t, ui
     ToeplitzPlan tp;
     if (!toeplitz_plan(n, m, &tp)) return fail(ctx, PA_EINVAL, "Toeplitz sizes out of range");
     Plan pl;
-    if (!make_plan(tp.len, &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    if (!plan_for(ctx, tp.len, &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     const uint64_t L = pl.L;
     int rc = ensure_caps(ctx, (L + kNumPrimes - 1) / kNumPrimes, 0);
     if (rc) return rc;
@@ -643,7 +655,6 @@ int enqueue_toeplitz(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* d_t, ui
     PassArgs base{};
     base.L = (uint32_t)L;
     base.tb = Tables{ctx->pass_lo, ctx->pass_hi};
-    base.rtw = ctx->rtw;
     base.store_limit = (uint32_t)L;
     base.primes = 1;
     for (uint64_t piece = 0; piece < tp.pieces; ++piece) {
@@ -729,6 +740,69 @@ int check_toeplitz(pa_ctx* ctx, uint64_t n, uint64_t m)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Plan geometry choice: explicit, or timed on the device (pa_tune)
+// ---------------------------------------------------------------------------
+namespace {
+
+bool same_plan(const Plan& a, const Plan& b)
+{
+    if (a.P != b.P) return false;
+    for (int i = 0; i < a.P; ++i) {
+        if (a.r[i] != b.r[i] || a.logC[i] != b.logC[i] || a.nsteps[i] != b.nsteps[i]) return false;
+        for (int k = 0; k < a.nsteps[i]; ++k)
+            if (a.steps[i][k] != b.steps[i][k]) return false;
+    }
+    return true;
+}
+
+void describe(const Plan& pl, pa_plan* out)
+{
+    out->tile_log = pl.t;
+    out->strided_tile_log = pl.P > 1 ? pl.ts : 0;
+    out->rows3_log = pl.f == 3 ? pl.r[0] : 0;
+    out->passes = pl.P;
+    out->ms = 0.f;
+}
+
+// Distinct valid geometries for length len: the default first, then those
+// with at most one pass more than the fewest possible, fewest passes and
+// largest tiles first.
+int candidates(Len len, pa_plan* out, int max)
+{
+    constexpr int kMaxFound = 256;
+    static thread_local Plan found[kMaxFound];
+    int cnt = 0;
+    Plan d;
+    const bool have_default = make_plan(len, &d);
+    if (have_default) found[cnt++] = d;
+    const int tlo = std::min(len.k, 10);
+    int min_p = have_default ? d.P : 99;
+    for (int t = kTileLog; t >= tlo; --t)
+        for (int ts = kTileLog; ts >= 10; --ts)
+            for (int r0 = (len.f == 3 ? kStridedMaxLog : 0); r0 >= (len.f == 3 ? 2 : 0); --r0) {
+                Plan pl;
+                if (!make_plan(len, &pl, 1, PlanParams{t, ts, r0})) continue;
+                bool dup = false;
+                for (int i = 0; i < cnt && !dup; ++i) dup = same_plan(found[i], pl);
+                if (dup || cnt >= kMaxFound) continue;
+                found[cnt++] = pl;
+                min_p = std::min(min_p, pl.P);
+            }
+    int order[kMaxFound];
+    int k = 0;
+    for (int i = 0; i < cnt; ++i)
+        if (i == 0 && have_default) order[k++] = i;
+    for (int P = min_p; P <= min_p + 1; ++P)
+        for (int i = have_default ? 1 : 0; i < cnt; ++i)
+            if (found[i].P == P) order[k++] = i;
+    const int n = std::min(k, max);
+    for (int i = 0; i < n; ++i) describe(found[order[i]], &out[i]);
+    return n;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pa_strerror(int status)
@@ -774,7 +848,6 @@ int pa_init(pa_ctx** out, int device)
     if (!ctx) return PA_ENOMEM;
     ctx->device = device;
     int rc = PA_OK;
-    uint2* h_tile = nullptr;
     uint32_t *h_lo = nullptr, *h_hi = nullptr;
     do {
         if (hipSetDevice(device) != hipSuccess) { rc = PA_ENODEV; break; }
@@ -790,24 +863,12 @@ int pa_init(pa_ctx** out, int device)
             rc = PA_EDEVICE;
             break;
         }
-        h_tile = new (std::nothrow) uint2[kNumPrimes * kRtw];
         h_lo = new (std::nothrow) uint32_t[kNumPrimes * 4096];
         h_hi = new (std::nothrow) uint32_t[kNumPrimes * kRootHi];
-        if (!h_tile || !h_lo || !h_hi) { rc = PA_ENOMEM; break; }
+        if (!h_lo || !h_hi) { rc = PA_ENOMEM; break; }
         for (int pi = 0; pi < kNumPrimes; ++pi) {
             const uint64_t p = kPrimes[pi];
-            const uint64_t g = generator(p);
-            const uint64_t wo = hpow(g, (p - 1) / kOrder, p);            // order 3 2^25
-            const uint64_t w6 = hpow(wo, kOrder / 64, p);                 // order 64
-            const uint64_t w6i = hpow(w6, p - 2, p);
-            for (int e = 0; e < 32; ++e) {
-                const uint64_t f = hpow(w6, e, p), b = hpow(w6i, e, p);
-                h_tile[pi * kRtw + e] = make_uint2((uint32_t)f, hshoup(f, p));
-                h_tile[pi * kRtw + 32 + e] = make_uint2((uint32_t)b, hshoup(b, p));
-            }
-            const uint64_t w3 = hpow(wo, kOrder / 3, p), w3i = w3 * w3 % p;   // cube roots
-            h_tile[pi * kRtw + 64] = make_uint2((uint32_t)w3, hshoup(w3, p));
-            h_tile[pi * kRtw + 65] = make_uint2((uint32_t)w3i, hshoup(w3i, p));
+            const uint64_t wo = kRoot[pi];                                 // order 3 2^25
             uint64_t w = 1;
             for (int i = 0; i < 4096; ++i) {
                 h_lo[pi * 4096 + i] = hmont(w, p);
@@ -820,15 +881,12 @@ int pa_init(pa_ctx** out, int device)
                 w = w * step % p;
             }
         }
-        if (hipMalloc(&ctx->rtw, sizeof(uint2) * kNumPrimes * kRtw) != hipSuccess ||
-            hipMalloc(&ctx->pass_lo, sizeof(uint32_t) * kNumPrimes * 4096) != hipSuccess ||
+        if (hipMalloc(&ctx->pass_lo, sizeof(uint32_t) * kNumPrimes * 4096) != hipSuccess ||
             hipMalloc(&ctx->pass_hi, sizeof(uint32_t) * kNumPrimes * kRootHi) != hipSuccess) {
             rc = PA_ENOMEM;
             break;
         }
-        if (hipMemcpy(ctx->rtw, h_tile, sizeof(uint2) * kNumPrimes * kRtw,
-                      hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(ctx->pass_lo, h_lo, sizeof(uint32_t) * kNumPrimes * 4096,
+        if (hipMemcpy(ctx->pass_lo, h_lo, sizeof(uint32_t) * kNumPrimes * 4096,
                       hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(ctx->pass_hi, h_hi, sizeof(uint32_t) * kNumPrimes * kRootHi,
                       hipMemcpyHostToDevice) != hipSuccess) {
@@ -836,7 +894,6 @@ int pa_init(pa_ctx** out, int device)
             break;
         }
     } while (0);
-    delete[] h_tile;
     delete[] h_lo;
     delete[] h_hi;
     if (rc != PA_OK) {
@@ -858,7 +915,6 @@ void pa_destroy(pa_ctx* ctx)
     (void)hipFree(ctx->d_c);
     (void)hipFree(ctx->d_d);
     (void)hipFree(ctx->tbits);
-    (void)hipFree(ctx->rtw);
     (void)hipFree(ctx->pass_lo);
     (void)hipFree(ctx->pass_hi);
     if (ctx->have_events)
@@ -963,6 +1019,7 @@ struct pa_mul {
     pa_ctx* ctx;
     uint64_t n;
     uint32_t* A;      // c-hat for blocks of n bits, scaled by 2^32 / L
+    Plan plan;        // the geometry c-hat was made with (its spectrum order)
 };
 
 int pa_mul_create(pa_ctx* ctx, uint64_t seed_a, const uint64_t* d_c, uint64_t n, void* stream,
@@ -979,12 +1036,13 @@ int pa_mul_create(pa_ctx* ctx, uint64_t seed_a, const uint64_t* d_c, uint64_t n,
         if ((w0 & 1) == 0) return fail(ctx, PA_EINVAL, "multiplier c must be odd");
     }
     Plan pl;
-    if (!make_plan(plan_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    if (!plan_for(ctx, plan_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     pa_mul* mh = new (std::nothrow) pa_mul;
     if (!mh) return PA_ENOMEM;
     mh->ctx = ctx;
     mh->n = n;
     mh->A = nullptr;
+    mh->plan = pl;
     const uint64_t L = pl.L;
     hipError_t e = hipMalloc(&mh->A, kNumPrimes * 4ull * L);
     if (e != hipSuccess) {
@@ -1020,8 +1078,7 @@ int pa_hash_mul_async(pa_ctx* ctx, const pa_mul* mh, const uint64_t* d_key, uint
     PA_HIP(ctx, hipSetDevice(ctx->device));
     rc = ensure_workspace(ctx, mh->n);
     if (rc) return rc;
-    Plan pl;
-    if (!make_plan(plan_len(mh->n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    const Plan& pl = mh->plan;
     const uint64_t n = mh->n;
     Work w;
     w.key = reinterpret_cast<const uint32_t*>(d_key);
@@ -1285,6 +1342,112 @@ int pa_toeplitz(pa_ctx* ctx, const uint64_t* key, const uint64_t* t, uint64_t se
     PA_HIP(ctx, hipMemcpyAsync(out, ctx->d_out, words_of(m) * 8, hipMemcpyDeviceToHost,
                                ctx->stream));
     PA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PA_OK;
+}
+
+int pa_plan_candidates(uint64_t n, pa_plan* out, int max)
+{
+    if (n == 0 || n > PA_MAX_N || !out || max <= 0) return 0;
+    return candidates(plan_len(n), out, max);
+}
+
+int pa_plan_get(pa_ctx* ctx, uint64_t n, pa_plan* out)
+{
+    int rc = check_sizes(ctx, n, 1);
+    if (rc) return rc;
+    if (!out) return fail(ctx, PA_EINVAL, "null plan");
+    Plan pl;
+    if (!plan_for(ctx, plan_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
+    describe(pl, out);
+    return PA_OK;
+}
+
+int pa_plan_set(pa_ctx* ctx, uint64_t n, const pa_plan* p)
+{
+    int rc = check_sizes(ctx, n, 1);
+    if (rc) return rc;
+    const Len len = plan_len(n);
+    const int slot = len_slot(len);
+    if (!p) {
+        ctx->plans[slot] = pa_ctx::PlanChoice{};
+        return PA_OK;
+    }
+    Plan pl;
+    const PlanParams pp{p->tile_log, p->strided_tile_log ? p->strided_tile_log : p->tile_log,
+                        len.f == 3 ? p->rows3_log : 0};
+    if (pp.t <= 0 || !make_plan(len, &pl, 1, pp))
+        return fail(ctx, PA_EINVAL, "plan geometry not valid for this length");
+    ctx->plans[slot] = pa_ctx::PlanChoice{pp.t, pp.ts, pp.r0};
+    return PA_OK;
+}
+
+int pa_tune(pa_ctx* ctx, uint64_t n, int reps, pa_plan* best)
+{
+    int rc = check_sizes(ctx, n, 1);
+    if (rc) return rc;
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    reps = std::max(1, std::min(reps, 100));
+    rc = ensure_workspace(ctx, n);
+    if (rc) return rc;
+    if (!ctx->have_events) {
+        for (auto& e : ctx->ev) PA_HIP(ctx, hipEventCreate(&e));
+        ctx->have_events = true;
+    }
+    pa_plan cand[64];
+    const Len len = plan_len(n);
+    const int nc = candidates(len, cand, 64);
+    if (nc == 0) return fail(ctx, PA_EINVAL, "internal: no plan");
+    const uint64_t m = std::max<uint64_t>(1, n / 2);
+    uint64_t *d_key = nullptr, *d_out = nullptr;
+    hipError_t e = hipMalloc(&d_key, words_of(n) * 8);
+    if (e == hipSuccess) e = hipMalloc(&d_out, words_of(m) * 8);
+    if (e != hipSuccess) {
+        (void)hipFree(d_key);
+        return fail(ctx, PA_ENOMEM, "tuning buffers", e);
+    }
+    const hipStream_t st = ctx->stream;
+    const int slot = len_slot(len);
+    int best_i = 0;
+    float best_ms = 0.f;
+    rc = PA_OK;
+    do {
+        if ((e = launch_stream_words(0x243F6A8885A308D3ull, words_of(n), d_key, st)) != hipSuccess)
+            break;
+        for (int i = 0; i < nc && rc == PA_OK; ++i) {
+            ctx->plans[slot] = pa_ctx::PlanChoice{cand[i].tile_log,
+                                                  cand[i].strided_tile_log ? cand[i].strided_tile_log
+                                                                           : cand[i].tile_log,
+                                                  cand[i].rows3_log};
+            rc = enqueue(ctx, d_key, nullptr, nullptr, 1, 2, n, m, d_out, st);
+            if (rc) break;
+            if ((e = hipEventRecord(ctx->ev[0], st)) != hipSuccess) break;
+            for (int r = 0; r < reps && rc == PA_OK; ++r)
+                rc = enqueue(ctx, d_key, nullptr, nullptr, 1, 2, n, m, d_out, st);
+            if ((e = hipEventRecord(ctx->ev[1], st)) != hipSuccess) break;
+            if ((e = hipEventSynchronize(ctx->ev[1])) != hipSuccess) break;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1])) != hipSuccess) break;
+            cand[i].ms = ms / reps;
+            if (i == 0 || cand[i].ms < best_ms) {
+                best_ms = cand[i].ms;
+                best_i = i;
+            }
+        }
+    } while (0);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(d_key);
+    (void)hipFree(d_out);
+    if (rc == PA_OK && e != hipSuccess) rc = fail(ctx, PA_EDEVICE, "pa_tune", e);
+    if (rc) {
+        ctx->plans[slot] = pa_ctx::PlanChoice{};
+        return rc;
+    }
+    ctx->plans[slot] = pa_ctx::PlanChoice{cand[best_i].tile_log,
+                                          cand[best_i].strided_tile_log
+                                              ? cand[best_i].strided_tile_log
+                                              : cand[best_i].tile_log,
+                                          cand[best_i].rows3_log};
+    if (best) *best = cand[best_i];
     return PA_OK;
 }
 

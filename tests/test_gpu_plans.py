@@ -1,0 +1,134 @@
+"""GPU tests of the transform geometries (pa_plan_*, pa_tune).
+
+Every geometry is a different set of kernel launches (tile sizes, rows of the
+factor-3 pass, register-step splits, two or three passes); each must give the
+oracle's result bit for bit.  The autotuner must keep a candidate and stay
+exact, and a cached multiplier must keep the geometry it was made with.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pa():
+    import paper_1910_04429_amd as pa
+    return pa
+
+
+@pytest.fixture(scope="module")
+def ctx(pa):
+    c = pa.pa_init(0)
+    yield c
+    pa.pa_destroy(c)
+
+
+def _hash(pa, ctx, torch, d_key, b):
+    d_out = torch.full((workloads.words(b.m),), -1, dtype=torch.int64, device="cuda")
+    pa.pa_hash_async(ctx, d_key, b.seed_a, b.seed_b, b.n, b.m, d_out)
+    torch.cuda.synchronize()
+    return d_out.cpu().numpy().view(np.uint64).copy()
+
+
+# 2^k lengths (one and two passes) and 3 2^k lengths (two and three passes)
+CASES = [(40_000, 9_999), (1_000_003, 99_999), (3_200_000, 1_000_001), (10_000_000, 2_000_000)]
+
+
+@pytest.mark.parametrize("n,m", CASES)
+def test_every_candidate_geometry_is_exact(pa, ctx, n, m):
+    import torch
+    b = workloads.single_block(31, n, m)
+    key = b.key()
+    want = oracle.pa_hash(key, b.seed_a, b.seed_b, n, m)
+    d_key = torch.from_numpy(key.view(np.int64)).cuda()
+    cands = pa.pa_plan_candidates(n)
+    assert cands and cands[0] == pa.pa_plan_get(ctx, n) | {"ms": 0.0}
+    try:
+        for c in cands:
+            _log(f"plan n={n} {c}")
+            pa.pa_plan_set(ctx, n, c)
+            got = pa.pa_plan_get(ctx, n)
+            assert (got["tile_log"], got["passes"]) == (c["tile_log"], c["passes"])
+            assert np.array_equal(_hash(pa, ctx, torch, d_key, b), want), c
+    finally:
+        pa.pa_plan_set(ctx, n, None)
+
+
+def test_n1e8_geometries(pa, ctx):
+    """The benchmark block under the 2-pass geometries and a few 3-pass ones."""
+    import torch
+    b = workloads.single("n1e8")
+    d_key = torch.from_numpy(b.key().view(np.int64)).cuda()
+    want = _hash(pa, ctx, torch, d_key, b)
+    cands = pa.pa_plan_candidates(b.n)
+    two = [c for c in cands if c["passes"] == 2]
+    three = [c for c in cands if c["passes"] == 3][:4]
+    try:
+        for c in two + three:
+            _log(f"plan n1e8 {c}")
+            pa.pa_plan_set(ctx, b.n, c)
+            assert np.array_equal(_hash(pa, ctx, torch, d_key, b), want), c
+    finally:
+        pa.pa_plan_set(ctx, b.n, None)
+    _log("n1e8 oracle")
+    assert np.array_equal(want, oracle.pa_hash(b.key(), b.seed_a, b.seed_b, b.n, b.m))
+
+
+def test_tune_keeps_a_candidate_and_stays_exact(pa, ctx):
+    import torch
+    b = workloads.single("n1e7")
+    best = pa.pa_tune(ctx, b.n, 2)
+    _log(f"tuned n1e7: {best}")
+    assert best["ms"] > 0
+    keys = [(c["tile_log"], c["strided_tile_log"], c["rows3_log"])
+            for c in pa.pa_plan_candidates(b.n)]
+    assert (best["tile_log"], best["strided_tile_log"], best["rows3_log"]) in keys
+    got = pa.pa_plan_get(ctx, b.n)
+    assert (got["tile_log"], got["strided_tile_log"], got["rows3_log"]) == \
+        (best["tile_log"], best["strided_tile_log"], best["rows3_log"])
+    d_key = torch.from_numpy(b.key().view(np.int64)).cuda()
+    try:
+        assert np.array_equal(_hash(pa, ctx, torch, d_key, b),
+                              oracle.pa_hash(b.key(), b.seed_a, b.seed_b, b.n, b.m))
+    finally:
+        pa.pa_plan_set(ctx, b.n, None)
+
+
+def test_cached_multiplier_keeps_its_geometry(pa, ctx):
+    import torch
+    n, m = 3_200_000, 777_777
+    b = workloads.single_block(32, n, m)
+    cands = [c for c in pa.pa_plan_candidates(n) if c["passes"] == 2]
+    assert len(cands) >= 2
+    d_key = torch.from_numpy(b.key().view(np.int64)).cuda()
+    d_out = torch.zeros(workloads.words(m), dtype=torch.int64, device="cuda")
+    try:
+        pa.pa_plan_set(ctx, n, cands[0])
+        mul = pa.pa_mul_create(ctx, b.seed_a, n)
+        pa.pa_plan_set(ctx, n, cands[-1])
+        pa.pa_hash_mul_async(ctx, mul, d_key, b.seed_b, n, m, d_out)
+        torch.cuda.synchronize()
+        pa.pa_mul_destroy(mul)
+    finally:
+        pa.pa_plan_set(ctx, n, None)
+    assert np.array_equal(d_out.cpu().numpy().view(np.uint64),
+                          oracle.pa_hash(b.key(), b.seed_a, b.seed_b, n, m))
+
+
+def test_invalid_geometry_is_rejected(pa, ctx):
+    for bad in [{"tile_log": 15}, {"tile_log": 14, "strided_tile_log": 3},
+                {"tile_log": 14, "strided_tile_log": 14, "rows3_log": 12}]:
+        with pytest.raises(pa.PAError) as e:
+            pa.pa_plan_set(ctx, 10**8, bad)
+        assert e.value.status == pa.PA_EINVAL
+    assert pa.pa_plan_get(ctx, 10**8) == pa.pa_plan_candidates(10**8)[0]
