@@ -438,8 +438,16 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
     const int N = (int)(R << logC);           // tile residues
     const uint32_t M = R << a.s;              // pass block length
     const int logCgs = a.s - logC;            // column groups per block
-    const uint32_t bg = blockIdx.x >> logCgs;
-    const uint32_t col0 = (blockIdx.x & ((1u << logCgs) - 1u)) << logC;
+    // Workgroups are dealt to the 8 XCDs round-robin by blockIdx.x, and each
+    // XCD has its own L2.  Adjacent column groups of a strided pass share
+    // 128-byte lines when a tile row is shorter than a line, so consecutive
+    // tiles go to one XCD (tile = (id mod 8) tiles/8 + id / 8, a bijection
+    // when the tile count is a multiple of 8) and each line is fetched once.
+    uint32_t tile = blockIdx.x;
+    if ((gridDim.x & 7u) == 0)
+        tile = (tile & 7u) * (gridDim.x >> 3) + (tile >> 3);
+    const uint32_t bg = tile >> logCgs;
+    const uint32_t col0 = (tile & ((1u << logCgs) - 1u)) << logC;
     const uint32_t blk0 = bg * M;             // global offset of the block
 
     // Tile element (row, c) <-> global position blk0 + row S + col0 + c; moved
