@@ -171,7 +171,9 @@ __device__ __forceinline__ uint32_t root_pow(const Tables& tb, uint32_t E)
 
 // LDS index of tile element e: XOR of bits 2..5 with bits 8..11, a bijection
 // that keeps 4-element groups together and spreads the strided step accesses
-// over the banks.
+// over the banks.  It is linear over GF(2): the elements of one small DFT sit
+// at base + n nstep with base and n nstep on disjoint bits, so their indices
+// are swz(base) ^ swz(n nstep), one vector XOR with a wave-uniform term.
 __device__ __forceinline__ uint32_t swz(uint32_t e) { return e ^ (((e >> 8) & 15u) << 2); }
 
 // Radix-2^R DIF butterflies in registers: natural input, bit-reversed output,
@@ -281,6 +283,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
         const uint32_t beta = (uint32_t)q >> (g.logC + g.logSig);
         const uint32_t base = (((beta << g.logB) + o) << g.logC) + c;
         const uint32_t nstep = 1u << (g.logSig + g.logC);
+        const uint32_t sb = swz(base);
         uint32_t x[RHO];
         uint32_t b = b_fixed;  // Montgomery form of the twiddle base
         if (twiddle && !fixed_base)
@@ -288,7 +291,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
         if (!kInv) {
 #pragma unroll
             for (int n = 0; n < RHO; ++n)
-                x[n] = sm[swz(base + n * nstep)];
+                x[n] = sm[sb ^ swz(n * nstep)];
             dif_regs<R, PI>(x);
             if (twiddle) {
                 uint32_t w = b;
@@ -301,11 +304,11 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
             }
 #pragma unroll
             for (int j = 0; j < RHO; ++j)
-                sm[swz(base + bitrev_c(j, R) * nstep)] = x[j];
+                sm[sb ^ swz(bitrev_c(j, R) * nstep)] = x[j];
         } else {
 #pragma unroll
             for (int j = 0; j < RHO; ++j)
-                x[j] = sm[swz(base + bitrev_c(j, R) * nstep)];
+                x[j] = sm[sb ^ swz(bitrev_c(j, R) * nstep)];
             if (twiddle) {
                 uint32_t w = b;
 #pragma unroll
@@ -318,7 +321,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
             dit_regs<R, PI>(x);
 #pragma unroll
             for (int n = 0; n < RHO; ++n)
-                sm[swz(base + n * nstep)] = x[n];
+                sm[sb ^ swz(n * nstep)] = x[n];
         }
     }
 }
@@ -347,7 +350,8 @@ __device__ __forceinline__ void run_step3(uint32_t* sm, int N, const StepGeo& g,
             b = root_pow<PI>(tb, step_exponent(g, o, c, kInv));
             b2 = fmul_mont(b, b, p, pneg);
         }
-        uint32_t x0 = sm[swz(base)], x1 = sm[swz(base + nstep)], x2 = sm[swz(base + 2 * nstep)];
+        const uint32_t s0 = swz(base), s1 = s0 ^ swz(nstep), s2 = s0 ^ swz(2 * nstep);
+        uint32_t x0 = sm[s0], x1 = sm[s1], x2 = sm[s2];
         if (kInv && twiddle) {
             x1 = fmul_mont(x1, b, p, pneg);
             x2 = fmul_mont(x2, b2, p, pneg);
@@ -360,9 +364,9 @@ __device__ __forceinline__ void run_step3(uint32_t* sm, int N, const StepGeo& g,
             y1 = fmul_mont(y1, b, p, pneg);
             y2 = fmul_mont(y2, b2, p, pneg);
         }
-        sm[swz(base)] = y0;
-        sm[swz(base + nstep)] = y1;
-        sm[swz(base + 2 * nstep)] = y2;
+        sm[s0] = y0;
+        sm[s1] = y1;
+        sm[s2] = y2;
     }
 }
 
