@@ -140,9 +140,11 @@ def ingest_counters(dirs, calib_mib, path=COUNTERS):
         out[f"{key}_kib_per_launch"] = float(np.mean(ntt))
         out[f"{key}_bytes_per_launch"] = float(np.mean(ntt)) * 1024 * factor
         out[f"{key}_kib_per_pass"] = [float(np.median(ntt[i::5])) for i in range(5)]
+    out["sq_per_pass"] = {}
     for counter, v in per.items():
         if counter.startswith("SQ_") or counter.startswith("GRBM_"):
             out["sq"][counter] = float(np.mean(v["k_pass"]))
+            out["sq_per_pass"][counter] = [float(np.median(v["k_pass"][i::5])) for i in range(5)]
     out["bytes_per_launch"] = int(out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"])
     with open(path, "w") as f:
         json.dump(out, f, indent=1)

@@ -99,8 +99,10 @@ int pa_hash_async(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_t 
 
 /*
  * Per-launch timing of one pa_hash_async call, for measurement.  The same
- * kernels run as in pa_hash_async; a HIP event is recorded on `stream` around
- * every launch and the call waits for the stream before returning.
+ * kernels run as in pa_hash_async on `stream`; each launch carries a start and
+ * stop event stamped by its own dispatch (hipExtLaunchKernelGGL, so nothing
+ * is queued between the kernels), and the call waits for the stream before
+ * returning.
  *   kind:  PA_K_* of each launch
  *   ms:    its duration from the events
  *   bytes: the bytes the launch must move at minimum (its algorithmic traffic)

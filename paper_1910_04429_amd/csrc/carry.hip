@@ -306,7 +306,7 @@ __global__ __launch_bounds__(1024) void k_carry_scan(CarryArgs a)
 }  // namespace
 
 #ifndef PA_CARRY_PER_LARGE
-#define PA_CARRY_PER_LARGE 16
+#define PA_CARRY_PER_LARGE 8
 #endif
 
 int carry_digits_per_thread(uint32_t num_digits)
@@ -314,38 +314,45 @@ int carry_digits_per_thread(uint32_t num_digits)
     return num_digits >= (1u << 18) ? PA_CARRY_PER_LARGE : 4;
 }
 
+template <typename K>
+void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t stream, const LaunchEvents& ev,
+                  const CarryArgs& a)
+{
+    if (ev.start)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, ev.start, ev.stop, 0, a);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, stream, a);
+}
+
 template <bool kApply>
-void launch_chunks(const CarryArgs& a, hipStream_t stream, unsigned batch)
+void launch_chunks(const CarryArgs& a, hipStream_t stream, unsigned batch, const LaunchEvents& ev)
 {
     const dim3 grid(a.chunks, batch);
     switch (a.per) {
-    case 16:
-        hipLaunchKernelGGL((k_carry<16, kApply>), grid, dim3(kCarryThreads), 0, stream, a);
-        break;
-    case 8:
-        hipLaunchKernelGGL((k_carry<8, kApply>), grid, dim3(kCarryThreads), 0, stream, a);
-        break;
-    default:
-        hipLaunchKernelGGL((k_carry<4, kApply>), grid, dim3(kCarryThreads), 0, stream, a);
-        break;
+    case 16: launch_timed(k_carry<16, kApply>, grid, dim3(kCarryThreads), stream, ev, a); break;
+    case 8: launch_timed(k_carry<8, kApply>, grid, dim3(kCarryThreads), stream, ev, a); break;
+    default: launch_timed(k_carry<4, kApply>, grid, dim3(kCarryThreads), stream, ev, a); break;
     }
 }
 
-hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned batch)
+hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned batch,
+                              const LaunchEvents& ev)
 {
-    launch_chunks<false>(a, stream, batch);
+    launch_chunks<false>(a, stream, batch, ev);
     return hipGetLastError();
 }
 
-hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch)
+hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch,
+                             const LaunchEvents& ev)
 {
-    hipLaunchKernelGGL(k_carry_scan, dim3(batch), dim3(1024), 0, stream, a);
+    launch_timed(k_carry_scan, dim3(batch), dim3(1024), stream, ev, a);
     return hipGetLastError();
 }
 
-hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream, unsigned batch)
+hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream, unsigned batch,
+                              const LaunchEvents& ev)
 {
-    launch_chunks<true>(a, stream, batch);
+    launch_chunks<true>(a, stream, batch, ev);
     return hipGetLastError();
 }
 

@@ -134,13 +134,23 @@ __device__ __forceinline__ uint32_t fmul_shoup(uint32_t x, uint32_t w, uint32_t 
     return min(r, r - p);
 }
 
-// a b 2^{-32} mod p (Montgomery reduction), a, b < p.
+// a b 2^{-32} mod p (Montgomery reduction), a < p and b < 2p (t < 2 p^2).
 __device__ __forceinline__ uint32_t fmul_mont(uint32_t a, uint32_t b, uint32_t p, uint32_t pneg)
 {
     uint64_t t = (uint64_t)a * b;
     uint32_t m = (uint32_t)t * pneg;
     uint32_t u = (uint32_t)((t + (uint64_t)m * p) >> 32);  // < 2p
     return min(u, u - p);
+}
+
+// a b 2^{-32} mod p, left in [0, 2p): for a < 2p and b < p the sum t + m p is
+// below 2 p^2 + 2^32 p, so the result is below p (2p / 2^32 + 1) < 2p.  Used
+// for chains of twiddle powers, which feed another multiply, never an add.
+__device__ __forceinline__ uint32_t fmul_mont_lazy(uint32_t a, uint32_t b, uint32_t p, uint32_t pneg)
+{
+    uint64_t t = (uint64_t)a * b;
+    uint32_t m = (uint32_t)t * pneg;
+    return (uint32_t)((t + (uint64_t)m * p) >> 32);
 }
 
 // v mod p for any 32-bit v (v < 3p for these primes).

@@ -1,6 +1,7 @@
 // Internal interface between the runtime and the kernels of libpa.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -114,10 +115,17 @@ struct CarryArgs {
     const JobDesc* jobs;       // batch mode: per-block fields from jobs[blockIdx.y]
 };
 
+// Optional timing of one launch: events stamped by the dispatch itself
+// (hipExtLaunchKernelGGL), so no extra packets sit between the kernels.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Digits per thread of the carry kernel for a block of D digits.
 int carry_digits_per_thread(uint32_t num_digits);
 
-hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch = 1);
+hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch = 1,
+                       const LaunchEvents& ev = {});
 
 // Toeplitz variant: out[j] (or out[j] ^ ..., accumulate) = the 64 bits
 // res[base + 64 j + l] & 1, l < 64, of the first m positions.
@@ -125,8 +133,11 @@ hipError_t launch_parity(const uint32_t* res, uint64_t base, uint64_t m, uint64_
                          int accumulate, hipStream_t stream);
 // out[i] = SplitMix64 output i of `seed`, i < words.
 hipError_t launch_stream_words(uint64_t seed, uint64_t words, uint64_t* out, hipStream_t stream);
-hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
-hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
-hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream, unsigned batch = 1);
+hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned batch = 1,
+                              const LaunchEvents& ev = {});
+hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch = 1,
+                             const LaunchEvents& ev = {});
+hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream, unsigned batch = 1,
+                              const LaunchEvents& ev = {});
 
 }  // namespace pa

@@ -299,7 +299,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
                 for (int k = 1; k < RHO; ++k) {
                     const int j = bitrev_c(k, R);
                     x[j] = fmul_mont(x[j], w, p, pneg);
-                    if (k + 1 < RHO) w = fmul_mont(w, b, p, pneg);
+                    if (k + 1 < RHO) w = fmul_mont_lazy(w, b, p, pneg);
                 }
             }
 #pragma unroll
@@ -315,7 +315,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
                 for (int k = 1; k < RHO; ++k) {
                     const int j = bitrev_c(k, R);
                     x[j] = fmul_mont(x[j], w, p, pneg);
-                    if (k + 1 < RHO) w = fmul_mont(w, b, p, pneg);
+                    if (k + 1 < RHO) w = fmul_mont_lazy(w, b, p, pneg);
                 }
             }
             dit_regs<R, PI>(x);
@@ -348,7 +348,7 @@ __device__ __forceinline__ void run_step3(uint32_t* sm, int N, const StepGeo& g,
         uint32_t b = 0, b2 = 0;
         if (twiddle) {
             b = root_pow<PI>(tb, step_exponent(g, o, c, kInv));
-            b2 = fmul_mont(b, b, p, pneg);
+            b2 = fmul_mont_lazy(b, b, p, pneg);
         }
         const uint32_t s0 = swz(base), s1 = s0 ^ swz(nstep), s2 = s0 ^ swz(2 * nstep);
         uint32_t x0 = sm[s0], x1 = sm[s1], x2 = sm[s2];
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
 
 }  // namespace
 
-hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch)
+hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch, const LaunchEvents& ev)
 {
     const uint32_t N = ((uint32_t)a.f << a.r) << a.logC;
     const unsigned tiles = a.L / N;
@@ -554,8 +554,12 @@ hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch)
     uint32_t threads = N / first;
     threads = threads < 64 ? 64 : (threads > kPassThreads ? kPassThreads : threads);
     const unsigned primes = a.primes > 0 && a.primes < kNumPrimes ? (unsigned)a.primes : kNumPrimes;
-    hipLaunchKernelGGL(k_pass, dim3(tiles, primes, batch), dim3(threads),
-                       sizeof(uint32_t) * N, stream, a);
+    if (ev.start)
+        hipExtLaunchKernelGGL(k_pass, dim3(tiles, primes, batch), dim3(threads),
+                              sizeof(uint32_t) * N, stream, ev.start, ev.stop, 0, a);
+    else
+        hipLaunchKernelGGL(k_pass, dim3(tiles, primes, batch), dim3(threads),
+                           sizeof(uint32_t) * N, stream, a);
     return hipGetLastError();
 }
 

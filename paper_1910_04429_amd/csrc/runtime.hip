@@ -213,31 +213,31 @@ int check_sizes(pa_ctx* ctx, uint64_t n, uint64_t m)
     return PA_OK;
 }
 
-// Optional per-launch event recording for pa_hash_profile.
+// Optional per-launch timing for pa_hash_profile: each launch gets an event
+// pair that its own dispatch stamps (no packets between the kernels).
 struct Recorder {
     pa_ctx* ctx;
     pa_profile* prof;
     hipStream_t stream;
-    hipError_t begin(int kind, uint64_t bytes)
+    hipError_t next(int kind, uint64_t bytes, LaunchEvents* ev)
     {
         const int i = prof->count;
         if (i >= PA_PROFILE_MAX) return hipErrorInvalidValue;
         prof->kind[i] = kind;
         prof->bytes[i] = bytes;
-        return hipEventRecord(ctx->ev[2 * i], stream);
-    }
-    hipError_t end()
-    {
-        const int i = prof->count++;
-        return hipEventRecord(ctx->ev[2 * i + 1], stream);
+        prof->count = i + 1;
+        ev->start = ctx->ev[2 * i];
+        ev->stop = ctx->ev[2 * i + 1];
+        return hipSuccess;
     }
 };
 
+// Launch `call`, which names the event pair ev_ (empty unless profiling).
 #define PA_LAUNCH(ctx, rec, kind, bytes, call)                                   \
     do {                                                                         \
-        if (rec) PA_HIP(ctx, (rec)->begin((kind), (bytes)));                     \
+        LaunchEvents ev_{};                                                      \
+        if (rec) PA_HIP(ctx, (rec)->next((kind), (bytes), &ev_));                \
         PA_HIP(ctx, call);                                                       \
-        if (rec) PA_HIP(ctx, (rec)->end());                                      \
     } while (0)
 
 // Transform plan for L = f 2^k: tile size, passes, register steps, output scale.
@@ -415,7 +415,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
             }
         }
         const uint64_t in = (i == 0) ? (w.c ? w.key_bytes : 0) : arr;
-        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + arr, launch_pass(a, stream, batch));
+        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + arr, launch_pass(a, stream, batch, ev_));
     }
     if (w.only_chat) return PA_OK;
     for (int i = 0; i < P; ++i) {                           // x-hat, pointwise, last inverse pass
@@ -436,7 +436,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
             in += arr;
             if (P == 1) outb = outD;
         }
-        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + outb, launch_pass(a, stream, batch));
+        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + outb, launch_pass(a, stream, batch, ev_));
     }
     for (int i = P - 2; i >= 0; --i) {                      // remaining inverse passes
         PassArgs a = base;
@@ -450,7 +450,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
             a.limit_to_digits = 1;
         }
         PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, arr + (i == 0 ? outD : arr),
-                  launch_pass(a, stream, batch));
+                  launch_pass(a, stream, batch, ev_));
     }
     CarryArgs ca{};
     ca.res = w.B;
@@ -472,10 +472,10 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     ca.out = w.out;
     ca.jobs = w.jobs;
     const uint64_t chunk_bytes = 4ull * w.chunks * batch;
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + chunk_bytes, launch_carry_local(ca, stream, batch));
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_SCAN, 2 * chunk_bytes, launch_carry_scan(ca, stream, batch));
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + chunk_bytes, launch_carry_local(ca, stream, batch, ev_));
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_SCAN, 2 * chunk_bytes, launch_carry_scan(ca, stream, batch, ev_));
     PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, outD + chunk_bytes + w.out_bytes,
-              launch_carry_apply(ca, stream, batch));
+              launch_carry_apply(ca, stream, batch, ev_));
     return PA_OK;
 }
 
