@@ -144,7 +144,9 @@ def ingest_counters(dirs, calib_mib, path=COUNTERS):
     for counter, v in per.items():
         if counter.startswith("SQ_") or counter.startswith("GRBM_"):
             out["sq"][counter] = float(np.mean(v["k_pass"]))
-            out["sq_per_pass"][counter] = [float(np.median(v["k_pass"][i::5])) for i in range(5)]
+            vals = v["k_pass"]
+            if len(vals) >= 5:
+                out["sq_per_pass"][counter] = [float(np.median(vals[i::5])) for i in range(5)]
     out["bytes_per_launch"] = int(out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"])
     with open(path, "w") as f:
         json.dump(out, f, indent=1)

@@ -13,7 +13,7 @@
 // adjacent columns per tile so that every row segment is a full 128-byte line.
 //
 // Inside a tile the length-R transform is itself split into steps of radix
-// 2^r <= 32.  A step loads each of its small DFTs from LDS into registers, runs
+// 2^r <= 16 (68 registers per lane: seven waves per SIMD).  A step loads each of its small DFTs from LDS into registers, runs
 // the radix-2 butterflies there with the omega_64 powers (compile-time
 // constants of the prime, so scalar immediates), multiplies output k by b^k
 // for a per-DFT base b, and writes back.  The kernel body is instantiated once
@@ -131,23 +131,47 @@ __device__ __forceinline__ BlockView block_view(const PassArgs& a)
     return v;
 }
 
-// Digit t of the operand described by the block's source (0 beyond the top digit).
-__device__ __forceinline__ uint32_t source_digit(const BlockView& a, uint32_t t)
+// Digits pos .. pos + 3 (pos a multiple of 4) of the operand described by the
+// block's source, 0 beyond the top digit: one 16-byte load of key digits, or
+// two SplitMix64 words of a seeded multiplier (bit 0 forced to 1, eq. (6)).
+__device__ __forceinline__ uint4 source_quad(const BlockView& a, uint32_t pos)
 {
-    if (t >= a.num_digits)
-        return 0;
-    uint32_t v;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t D = a.num_digits;
+    if (pos >= D)
+        return v;
     if (a.src == kSrcDigits) {
-        v = a.digits[t];
+        if (pos + 4 <= D && (reinterpret_cast<uintptr_t>(a.digits) & 15u) == 0) {
+            v = *reinterpret_cast<const uint4*>(a.digits + pos);
+        } else {
+            v.x = a.digits[pos];
+            if (pos + 1 < D) v.y = a.digits[pos + 1];
+            if (pos + 2 < D) v.z = a.digits[pos + 2];
+            if (pos + 3 < D) v.w = a.digits[pos + 3];
+        }
     } else {
-        const uint64_t w = splitmix64(a.seed, t >> 1);
-        v = (t & 1) ? (uint32_t)(w >> 32) : (uint32_t)w;
-        if (t == 0)
-            v |= 1u;  // the multiplier must be odd (eq. (6))
+        const uint64_t w0 = splitmix64(a.seed, pos >> 1);
+        v.x = (uint32_t)w0 | (pos == 0 ? 1u : 0u);
+        v.y = (uint32_t)(w0 >> 32);
+        if (pos + 2 < D) {
+            const uint64_t w1 = splitmix64(a.seed, (pos >> 1) + 1);
+            v.z = (uint32_t)w1;
+            v.w = (uint32_t)(w1 >> 32);
+        }
+        if (pos + 1 >= D) v.y = 0;
+        if (pos + 3 >= D) v.w = 0;
     }
+    // bits past n in the top digit
     const uint32_t top = (uint32_t)(a.n & 31);
-    if (t == a.num_digits - 1 && top)
-        v &= (1u << top) - 1u;
+    if (top && D - 1 - pos < 4u) {
+        const uint32_t mask = (1u << top) - 1u;
+        switch (D - 1 - pos) {
+        case 0: v.x &= mask; break;
+        case 1: v.y &= mask; break;
+        case 2: v.z &= mask; break;
+        default: v.w &= mask; break;
+        }
+    }
     return v;
 }
 
@@ -378,7 +402,6 @@ __device__ __forceinline__ void dispatch_step(int r, uint32_t* sm, int N, const 
     case 2: run_step<2, kInv, PI>(sm, N, g, tb); break;
     case 3: run_step<3, kInv, PI>(sm, N, g, tb); break;
     case 4: run_step<4, kInv, PI>(sm, N, g, tb); break;
-    case 5: run_step<5, kInv, PI>(sm, N, g, tb); break;
     default: break;
     }
 }
@@ -477,10 +500,11 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
             v.z = source_bit(bv, pos + 2);
             v.w = source_bit(bv, pos + 3);
         } else {
-            v.x = freduce32(source_digit(bv, pos + 0), p);
-            v.y = freduce32(source_digit(bv, pos + 1), p);
-            v.z = freduce32(source_digit(bv, pos + 2), p);
-            v.w = freduce32(source_digit(bv, pos + 3), p);
+            v = source_quad(bv, pos);
+            v.x = freduce32(v.x, p);
+            v.y = freduce32(v.y, p);
+            v.z = freduce32(v.z, p);
+            v.w = freduce32(v.w, p);
         }
         *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
     }

@@ -91,13 +91,14 @@ uint64_t status_words(uint64_t D) { return 2 * ((D + kCarryThreads * 4 - 1) / (k
 #ifndef PA_TILE_SLACK
 #define PA_TILE_SLACK 8
 #endif
-constexpr int kTileDefaultLog = 13;
+constexpr int kTileDefaultLog = 12;
 
 // Default contiguous tile (log2 residues) for a transform of about 2^l
-// residues run for `blocks` blocks at once.  Tiles of 2^13 (32 KB of LDS) let
-// five workgroups share a CU, against two for 2^14, which keeps the last wave
-// of workgroups short; a lone short transform takes smaller tiles so that it
-// still spreads over the chip.  pa_tune measures instead of guessing.
+// residues run for `blocks` blocks at once.  Tiles of 2^12 (16 KB of LDS,
+// three radix-16 steps) leave occupancy to the register budget (seven
+// workgroups of four waves per CU) and keep the last wave of workgroups
+// short; a lone short transform takes smaller tiles so that it still spreads
+// over the chip.  pa_tune measures instead of guessing.
 int plan_tile(int l, unsigned blocks = 1)
 {
     if (l <= kTileMinLog) return l;
@@ -125,17 +126,16 @@ int plan_passes(int l, int t, int ts, int* r)
     return k + 1;
 }
 
-// Register steps of a length-2^r in-tile transform in a tile of 2^t residues:
-// radix up to 32 in big tiles (a radix-64 step needs 64 twiddle constants in
-// scalar registers and twice the vector registers); smaller radices (more,
-// shorter DFTs per step) in small tiles, which have too few threads to hide
-// the latency of long ones.
+// Register steps of a length-2^r in-tile transform: radix up to 16.  Larger
+// register radices need more vector registers per lane (radix 32: 94, five
+// waves per SIMD; radix 16: 68, seven) and the occupancy is worth more than
+// the saved LDS round trips (measured).
 // The contiguous pass splits greedily (its last step has no twiddles, so a
 // small last radix is cheap); strided passes split evenly, since every one of
 // their steps carries twiddles and a lopsided split leaves threads idle.
-int plan_steps(int r, int t, int* st, bool strided)
+int plan_steps(int r, int* st, bool strided)
 {
-    const int rmax = t >= 12 ? 5 : 4;
+    const int rmax = 4;
     const int k = (r + rmax - 1) / rmax;
     if (strided) {
         for (int i = 0; i < k; ++i) st[i] = r / k + (i < r % k ? 1 : 0);
@@ -262,9 +262,9 @@ bool make_plan(Len len, Plan* pl, unsigned blocks = 1, PlanParams pp = {})
     pl->k = len.k;
     pl->L = len.L();
     const int t = pp.t ? pp.t : plan_tile(len.k + (len.f == 3 ? 2 : 0), blocks);
-    // strided tiles: the full 64 KB for the factor-3 pass of long transforms
-    // (3 2^8 rows of 16 columns at 2^13 contiguous tiles), else as contiguous
-    const int ts = pp.ts ? pp.ts : ((len.f == 3 && t >= kTileDefaultLog) ? kTileLog : t);
+    // strided tiles: one size up for the factor-3 pass of long transforms
+    // (3 2^9 rows of 8 columns at 2^12 contiguous tiles), else as contiguous
+    const int ts = pp.ts ? pp.ts : ((len.f == 3 && t >= kTileDefaultLog) ? t + 1 : t);
     if (t > kTileLog || ts > kTileLog || ts < 6 || t < 1) return false;
     pl->t = t;
     pl->ts = ts;
@@ -300,7 +300,7 @@ bool make_plan(Len len, Plan* pl, unsigned blocks = 1, PlanParams pp = {})
         else
             pl->logC[i] = 0;
         if (strided && (pl->logC[i] < 2 || pl->logC[i] > pl->s[i])) return false;
-        pl->nsteps[i] = plan_steps(pl->r[i], strided ? ts : t, pl->steps[i], strided);
+        pl->nsteps[i] = plan_steps(pl->r[i], pl->steps[i], strided);
         if (pl->nsteps[i] > kMaxSteps) return false;
     }
     // c-hat is scaled on its last pass by 2^32 / L so that the Montgomery
