@@ -90,6 +90,11 @@ struct PassArgs {
     uint32_t scale_w[kNumPrimes], scale_q[kNumPrimes];
     Tables tb;
     int primes;                // primes transformed (grid.y); 0 means all kNumPrimes
+    // dual launch (single block, grid.z = 2, seeded multiplier): workgroups with
+    // blockIdx.z == 1 run the key's first pass, of the same geometry, with the
+    // key digits in `digits` and its spectrum in `other` (both unused by the
+    // multiplier's seeded forward pass)
+    int dual;
     // batch mode (jobs != null): per-block fields come from jobs[blockIdx.z]
     const JobDesc* jobs;
     int role;

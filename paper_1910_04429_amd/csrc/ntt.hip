@@ -127,6 +127,9 @@ __device__ __forceinline__ BlockView block_view(const PassArgs& a)
         }
         if (a.limit_to_digits)
             v.store_limit = (j.num_digits + 3u) & ~3u;
+    } else if (a.dual && blockIdx.z == 1) {
+        v.data = const_cast<uint32_t*>(a.other);
+        v.src = kSrcDigits;
     }
     return v;
 }

@@ -391,6 +391,9 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     auto geometry = [&](PassArgs& a, int i) { pass_geometry(a, pl, i); };
     const uint32_t limit = (uint32_t)((digits_of(w.n) + 3) & ~3ull);
 
+    // The first passes of c and of x share their geometry and are independent:
+    // one launch runs both (grid.z = 2), so each fills the other's last wave.
+    const bool dual = !w.jobs && !w.have_chat && !w.only_chat && P >= 2 && w.c == nullptr;
     for (int i = 0; i < P && !w.have_chat; ++i) {          // c-hat
         PassArgs a = base;
         a.role = kRoleMul;
@@ -414,11 +417,21 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
                 a.scale_q[pi] = pl.scale_q[pi];
             }
         }
-        const uint64_t in = (i == 0) ? (w.c ? w.key_bytes : 0) : arr;
-        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + arr, launch_pass(a, stream, batch, ev_));
+        uint64_t in = (i == 0) ? (w.c ? w.key_bytes : 0) : arr;
+        uint64_t outb = arr;
+        unsigned z = batch;
+        if (i == 0 && dual) {
+            a.dual = 1;
+            a.other = w.B;
+            a.digits = w.key;
+            in += w.key_bytes;
+            outb += arr;
+            z = 2;
+        }
+        PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + outb, launch_pass(a, stream, z, ev_));
     }
     if (w.only_chat) return PA_OK;
-    for (int i = 0; i < P; ++i) {                           // x-hat, pointwise, last inverse pass
+    for (int i = (dual ? 1 : 0); i < P; ++i) {              // x-hat, pointwise, last inverse pass
         PassArgs a = base;
         a.role = kRoleKey;
         a.data = w.B;
