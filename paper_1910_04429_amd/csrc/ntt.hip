@@ -438,13 +438,14 @@ __device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int si, uint32_t 
     return g;
 }
 
+// Steps 0 .. count-1 of the pass (forward), or their inverse count-1 .. 0.
 template <bool kInv, int PI>
-__device__ __forceinline__ void run_pass_steps(const PassArgs& a, uint32_t* sm, int N, uint32_t col0)
+__device__ __forceinline__ void run_pass_steps(const PassArgs& a, uint32_t* sm, int N, uint32_t col0,
+                                               int count)
 {
     const int has3 = a.f == 3;
-    const int total = a.nsteps + has3;
-    for (int k = 0; k < total; ++k) {
-        const int si = kInv ? total - 1 - k : k;
+    for (int k = 0; k < count; ++k) {
+        const int si = kInv ? count - 1 - k : k;
         const StepGeo g = step_geo(a, si, col0);
         if (has3 && si == 0)
             run_step3<kInv, PI>(sm, N, g, a.tb);
@@ -455,11 +456,67 @@ __device__ __forceinline__ void run_pass_steps(const PassArgs& a, uint32_t* sm, 
     }
 }
 
+// The middle of the fused pass in registers: the last forward step of a
+// contiguous pass (radix 2^R over 2^R consecutive residues, no twiddles), the
+// pointwise product with c-hat (same positions) and the first inverse step,
+// which reads exactly the registers the forward step would have written.
+template <int R, int PI>
+__device__ __forceinline__ void fused_middle(uint32_t* sm, int N, const uint32_t* chat)
+{
+    constexpr uint32_t p = PrimeConst<PI>::p, pneg = PrimeConst<PI>::pneg;
+    constexpr int RHO = 1 << R;
+    const int ndft = N >> R;
+    for (int q = threadIdx.x; q < ndft; q += blockDim.x) {
+        const uint32_t base = (uint32_t)q << R;
+        const uint32_t sb = swz(base);
+        uint32_t x[RHO];
+#pragma unroll
+        for (int n = 0; n < RHO; ++n)
+            x[n] = sm[sb ^ swz((uint32_t)n)];
+        dif_regs<R, PI>(x);
+        uint32_t c[RHO];
+        if (RHO >= 4) {
+#pragma unroll
+            for (int v = 0; v < RHO / 4; ++v) {
+                const uint4 w = *reinterpret_cast<const uint4*>(chat + base + 4 * v);
+                c[4 * v] = w.x;
+                c[4 * v + 1] = w.y;
+                c[4 * v + 2] = w.z;
+                c[4 * v + 3] = w.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RHO; ++k) c[k] = chat[base + k];
+        }
+#pragma unroll
+        for (int k = 0; k < RHO; ++k) {
+            const int j = bitrev_c(k, R);
+            x[j] = fmul_mont(x[j], c[k], p, pneg);
+        }
+        dit_regs<R, PI>(x);
+#pragma unroll
+        for (int n = 0; n < RHO; ++n)
+            sm[sb ^ swz((uint32_t)n)] = x[n];
+    }
+}
+
+template <int PI>
+__device__ __forceinline__ void dispatch_fused_middle(int r, uint32_t* sm, int N, const uint32_t* chat)
+{
+    switch (r) {
+    case 1: fused_middle<1, PI>(sm, N, chat); break;
+    case 2: fused_middle<2, PI>(sm, N, chat); break;
+    case 3: fused_middle<3, PI>(sm, N, chat); break;
+    case 4: fused_middle<4, PI>(sm, N, chat); break;
+    default: break;
+    }
+}
+
 // One pass over the tile of prime PI owned by this workgroup.
 template <int PI>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
 {
-    constexpr uint32_t p = PrimeConst<PI>::p, pneg = PrimeConst<PI>::pneg;
+    constexpr uint32_t p = PrimeConst<PI>::p;
     const BlockView bv = block_view(a);
     uint32_t* data = bv.data + (size_t)PI * a.L;
 
@@ -513,27 +570,22 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
     }
     __syncthreads();
 
+    const int total = a.nsteps + (a.f == 3);
     if (a.mode == kInverse) {
-        run_pass_steps<true, PI>(a, sm, N, col0);
+        run_pass_steps<true, PI>(a, sm, N, col0, total);
+    } else if (a.mode == kFused) {
+        // Forward steps but the last, then the last forward step, the
+        // pointwise product with the pre-scaled c-hat (same layout) and the
+        // first inverse step together in registers, then the other inverse
+        // steps.  The fused pass is the contiguous last pass (f = 1, no pass
+        // twiddle), so its last step carries no twiddles.
+        run_pass_steps<false, PI>(a, sm, N, col0, total - 1);
+        const int rl = (int)((a.steps_code >> (4 * (a.nsteps - 1))) & 15u);
+        dispatch_fused_middle<PI>(rl, sm, N, bv.other + (size_t)PI * a.L + blk0);
+        __syncthreads();
+        run_pass_steps<true, PI>(a, sm, N, col0, total - 1);
     } else {
-        run_pass_steps<false, PI>(a, sm, N, col0);
-        if (a.mode == kFused) {
-            // Pointwise product with the pre-scaled c-hat (same layout), then
-            // the inverse of this pass.
-            const uint32_t* other = bv.other + (size_t)PI * a.L;
-            for (int u = threadIdx.x; u < nq; u += blockDim.x) {
-                const uint32_t e = (uint32_t)u << 2;
-                const uint4 cv = *reinterpret_cast<const uint4*>(other + blk0 + e);
-                uint4 v = *reinterpret_cast<uint4*>(&sm[swz(e)]);
-                v.x = fmul_mont(v.x, cv.x, p, pneg);
-                v.y = fmul_mont(v.y, cv.y, p, pneg);
-                v.z = fmul_mont(v.z, cv.z, p, pneg);
-                v.w = fmul_mont(v.w, cv.w, p, pneg);
-                *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
-            }
-            __syncthreads();
-            run_pass_steps<true, PI>(a, sm, N, col0);
-        }
+        run_pass_steps<false, PI>(a, sm, N, col0, total);
     }
 
     for (int u = threadIdx.x; u < nq; u += blockDim.x) {
