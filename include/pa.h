@@ -111,8 +111,8 @@ int pa_hash_async(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_t 
 enum pa_kernel_kind {
     PA_K_NTT_PASS = 0,    /* one LDS pass of a forward, fused or inverse NTT */
     PA_K_CARRY_LOCAL = 1, /* CRT + addend + column sums -> carry function per chunk */
-    PA_K_CARRY_SCAN = 2,  /* carry entering every chunk */
-    PA_K_CARRY_APPLY = 3, /* CRT + addend + carry resolve + mod 2^n + top-m bits */
+    PA_K_CARRY_SCAN = 2,  /* reserved: each apply workgroup now forms its chunk's carry-in itself */
+    PA_K_CARRY_APPLY = 3, /* carry-in from the chunk functions, CRT + addend + resolve + mod 2^n + top-m */
 };
 typedef struct pa_profile {
     int count;

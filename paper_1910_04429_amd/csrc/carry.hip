@@ -120,7 +120,6 @@ __device__ __forceinline__ void bind_job(CarryArgs& a, uint32_t job)
         a.seed = j.seed_b;
     }
     a.desc = j.carry;
-    a.carry_in = j.carry + j.chunks;
     a.out = j.out;
     a.chunks = j.chunks;
 }
@@ -231,7 +230,26 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
             a.desc[chunk] = f;
         return;
     }
-    const uint32_t cin_chunk = a.carry_in[chunk];
+    // carry entering this chunk: the functions of chunks 0 .. chunk-1 (written
+    // by the local kernel) composed in order and applied to carry 0; each
+    // workgroup reads the few thousand bytes itself instead of waiting for a
+    // separate scan launch
+    __shared__ uint32_t pre[kCarryThreads];
+    {
+        const uint32_t per_t = (chunk + kCarryThreads - 1) / kCarryThreads;
+        const uint32_t lo = (uint32_t)tid * per_t;
+        uint32_t g = kIdentity;
+        for (uint32_t k = lo; k < lo + per_t && k < chunk; ++k)
+            g = compose(g, a.desc[k]);
+        pre[tid] = g;
+        __syncthreads();
+        for (int d = 1; d < kCarryThreads; d <<= 1) {
+            if ((tid & (2 * d - 1)) == 0)
+                pre[tid] = compose(pre[tid], pre[tid + d]);
+            __syncthreads();
+        }
+    }
+    const uint32_t cin_chunk = apply(pre[0], 0u);
 
     // resolve this thread's digits; V digits of the chunk (and two past it) to LDS
     uint64_t carry = tid ? apply(scan[tid - 1], cin_chunk) : cin_chunk;
@@ -275,34 +293,6 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     }
 }
 
-// One workgroup: the carry into every chunk from the chunk functions.
-__global__ __launch_bounds__(1024) void k_carry_scan(CarryArgs a)
-{
-    __shared__ uint32_t sh[1024];
-    if (a.jobs)
-        bind_job(a, blockIdx.x);
-    const int tid = threadIdx.x;
-    const uint32_t per = (a.chunks + 1023) / 1024;
-    const uint32_t j0 = tid * per;
-    uint32_t f = kIdentity;
-    for (uint32_t j = j0; j < j0 + per && j < a.chunks; ++j)
-        f = compose(f, a.desc[j]);
-    sh[tid] = f;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const uint32_t prev = (tid >= d) ? sh[tid - d] : kIdentity;
-        __syncthreads();
-        f = compose(prev, f);
-        sh[tid] = f;
-        __syncthreads();
-    }
-    uint32_t c = tid ? apply(sh[tid - 1], 0) : 0u;
-    for (uint32_t j = j0; j < j0 + per && j < a.chunks; ++j) {
-        a.carry_in[j] = c;
-        c = apply(a.desc[j], c);
-    }
-}
-
 }  // namespace
 
 #ifndef PA_CARRY_PER_LARGE
@@ -339,13 +329,6 @@ hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned b
                               const LaunchEvents& ev)
 {
     launch_chunks<false>(a, stream, batch, ev);
-    return hipGetLastError();
-}
-
-hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch,
-                             const LaunchEvents& ev)
-{
-    launch_timed(k_carry_scan, dim3(batch), dim3(1024), stream, ev, a);
     return hipGetLastError();
 }
 

@@ -113,7 +113,6 @@ struct CarryArgs {
     const uint32_t* addend;    // kSrcDigits
     uint64_t seed;             // kSrcSeed
     uint32_t* desc;            // [chunks] carry function of each chunk
-    uint32_t* carry_in;        // [chunks] carry entering each chunk
     uint64_t* out;             // ceil(m / 64) words
     uint32_t chunks;           // grid width (the largest chunk count in a batch)
     int per;                   // digits per thread (4, 8 or 16)
@@ -140,8 +139,6 @@ hipError_t launch_parity(const uint32_t* res, uint64_t base, uint64_t m, uint64_
 hipError_t launch_stream_words(uint64_t seed, uint64_t words, uint64_t* out, hipStream_t stream);
 hipError_t launch_carry_local(const CarryArgs& a, hipStream_t stream, unsigned batch = 1,
                               const LaunchEvents& ev = {});
-hipError_t launch_carry_scan(const CarryArgs& a, hipStream_t stream, unsigned batch = 1,
-                             const LaunchEvents& ev = {});
 hipError_t launch_carry_apply(const CarryArgs& a, hipStream_t stream, unsigned batch = 1,
                               const LaunchEvents& ev = {});
 

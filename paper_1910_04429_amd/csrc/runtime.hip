@@ -481,12 +481,10 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     ca.chunks = w.chunks;
     ca.per = w.per;
     ca.desc = w.carry;
-    ca.carry_in = w.carry ? w.carry + w.chunks : nullptr;
     ca.out = w.out;
     ca.jobs = w.jobs;
     const uint64_t chunk_bytes = 4ull * w.chunks * batch;
     PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + chunk_bytes, launch_carry_local(ca, stream, batch, ev_));
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_SCAN, 2 * chunk_bytes, launch_carry_scan(ca, stream, batch, ev_));
     PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, outD + chunk_bytes + w.out_bytes,
               launch_carry_apply(ca, stream, batch, ev_));
     return PA_OK;
