@@ -109,12 +109,26 @@ def _counter_rows(d):
     return rows
 
 
+def _last_hashes(disps, hashes=3):
+    """The k_pass values of the last `hashes` complete hashes: runs of k_pass
+    dispatches that end at a carry kernel (one hash = one run)."""
+    runs, cur = [], []
+    for _, (name, v) in sorted(disps.items()):
+        if "k_pass" in name:
+            cur.append(v)
+        elif "k_carry" in name and cur:
+            runs.append(cur)
+            cur = []
+    runs = [r for r in runs if len(r) == len(runs[-1])] if runs else []
+    return runs[-hashes:]
+
+
 def ingest_counters(dirs, calib_mib, path=COUNTERS):
     """Per-launch HBM traffic of k_pass from FETCH_SIZE / WRITE_SIZE runs (KiB per
     dispatch), each scaled by what the same counter reads for the calibration
-    kernel, which reads and writes exactly calib_mib MiB.  Only the last 15
-    k_pass dispatches count (three hashes of five passes: the end of the timed
-    steps and the per-launch profile, all on one geometry)."""
+    kernel, which reads and writes exactly calib_mib MiB.  Only the k_pass
+    launches of the last three hashes count (the end of the timed steps and the
+    per-launch profile, all on one geometry)."""
     known_kib = calib_mib * 1024.0
     out = {"kernel": "k_pass", "workload": "n1e8", "source_hash": kernel_source_hash(),
            "calibration": {"kernel": "bitwise_not on int64 (reads and writes the given size)",
@@ -125,28 +139,34 @@ def ingest_counters(dirs, calib_mib, path=COUNTERS):
         for disp, name, counter, val in _counter_rows(d):
             per_counter.setdefault(counter, {}).setdefault(disp, [name, 0.0])[1] += val
         for counter, disps in per_counter.items():
-            ntt = [v for _, (nm, v) in sorted(disps.items()) if "k_pass" in nm][-15:]
+            hashes = _last_hashes(disps)
             cal = [v for _, (nm, v) in sorted(disps.items()) if "bitwise_not" in nm]
-            per[counter] = {"k_pass": ntt, "calib": cal}
+            per[counter] = {"hashes": hashes, "calib": cal}
+    npass = None
     for counter, key in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         if counter not in per:
             raise SystemExit(f"{counter} missing from {dirs}")
-        ntt, cal = per[counter]["k_pass"], per[counter]["calib"]
-        if not ntt or not cal:
-            raise SystemExit(f"{counter}: no k_pass or calibration dispatches")
+        hashes, cal = per[counter]["hashes"], per[counter]["calib"]
+        if not hashes or not cal:
+            raise SystemExit(f"{counter}: no k_pass hashes or calibration dispatches")
+        npass = len(hashes[0])
         factor = known_kib / float(np.median(cal))
+        flat = [v for h in hashes for v in h]
         out["calibration"][f"{key}_kib_read"] = float(np.median(cal))
         out["calibration"][f"{key}_factor"] = round(factor, 4)
-        out[f"{key}_kib_per_launch"] = float(np.mean(ntt))
-        out[f"{key}_bytes_per_launch"] = float(np.mean(ntt)) * 1024 * factor
-        out[f"{key}_kib_per_pass"] = [float(np.median(ntt[i::5])) for i in range(5)]
+        out[f"{key}_kib_per_launch"] = float(np.mean(flat))
+        out[f"{key}_bytes_per_launch"] = float(np.mean(flat)) * 1024 * factor
+        out[f"{key}_kib_per_pass"] = [float(np.median([h[i] for h in hashes])) for i in range(npass)]
+    out["passes_per_hash"] = npass
     out["sq_per_pass"] = {}
     for counter, v in per.items():
         if counter.startswith("SQ_") or counter.startswith("GRBM_"):
-            out["sq"][counter] = float(np.mean(v["k_pass"]))
-            vals = v["k_pass"]
-            if len(vals) >= 5:
-                out["sq_per_pass"][counter] = [float(np.median(vals[i::5])) for i in range(5)]
+            flat = [x for h in v["hashes"] for x in h]
+            out["sq"][counter] = float(np.mean(flat)) if flat else None
+            if v["hashes"]:
+                n = len(v["hashes"][0])
+                out["sq_per_pass"][counter] = [float(np.median([h[i] for h in v["hashes"]]))
+                                               for i in range(n)]
     out["bytes_per_launch"] = int(out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"])
     with open(path, "w") as f:
         json.dump(out, f, indent=1)

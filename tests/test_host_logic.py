@@ -132,24 +132,36 @@ def _write_counter_csv(d, counter, rows):
 
 def test_counter_ingest_scales_by_the_calibration_kernel(tmp_path):
     """bench.py's counter ingest: per-launch k_pass bytes = mean FETCH (KiB) x
-    (known calibration KiB / calibration FETCH) + the same for WRITE."""
+    (known calibration KiB / calibration FETCH) + the same for WRITE, over the
+    k_pass launches of the last three hashes (runs ended by a carry kernel)."""
     import sys
     sys.path.insert(0, ROOT)
     import bench
     calib = "at::native::bitwise_not_kernel"
-    kp = "pa::k_pass(pa::PassArgs)"
-    fetch = [(1, calib, 1024.0)] + [(2 + i, kp, 100.0 * (i % 5 + 1)) for i in range(10)]
-    write = [(1, calib, 4096.0)] + [(2 + i, kp, 50.0) for i in range(10)]
+    kp, kc = "pa::k_pass(pa::PassArgs)", "pa::k_carry<8, true>(pa::CarryArgs)"
+
+    def seq(values_per_pass):
+        rows, d = [(1, calib, None)], 2
+        for _ in range(4):                               # four hashes of four passes
+            for v in values_per_pass:
+                rows.append((d, kp, v)); d += 1
+            rows.append((d, kc, 1.0)); d += 1
+        return rows
+    fetch = [(i, n, 1024.0 if v is None else v) for i, n, v in seq([100.0, 200.0, 300.0, 400.0])]
+    write = [(i, n, 4096.0 if v is None else v) for i, n, v in seq([50.0] * 4)]
     _write_counter_csv(tmp_path / "f", "FETCH_SIZE", fetch)
     _write_counter_csv(tmp_path / "w", "WRITE_SIZE", write)
-    _write_counter_csv(tmp_path / "s", "SQ_INSTS_VALU", [(1, calib, 7.0), (2, kp, 10.0), (3, kp, 30.0)])
+    _write_counter_csv(tmp_path / "s", "SQ_INSTS_VALU",
+                       [(i, n, 7.0 if v is None else v) for i, n, v in seq([10.0, 30.0, 10.0, 30.0])])
     out = bench.ingest_counters([str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "s")],
                                 4, path=str(tmp_path / "c.json"))
     # 4 MiB = 4096 KiB known: fetch factor 4, write factor 1
     assert out["calibration"]["fetch_factor"] == 4.0 and out["calibration"]["write_factor"] == 1.0
-    assert out["fetch_kib_per_pass"] == [100.0, 200.0, 300.0, 400.0, 500.0]
-    assert out["bytes_per_launch"] == int(300.0 * 1024 * 4 + 50.0 * 1024)
+    assert out["passes_per_hash"] == 4
+    assert out["fetch_kib_per_pass"] == [100.0, 200.0, 300.0, 400.0]
+    assert out["bytes_per_launch"] == int(250.0 * 1024 * 4 + 50.0 * 1024)
     assert out["sq"]["SQ_INSTS_VALU"] == 20.0
+    assert out["sq_per_pass"]["SQ_INSTS_VALU"] == [10.0, 30.0, 10.0, 30.0]
 
 
 def test_toeplitz_plan_covers_the_needed_slice():
