@@ -53,10 +53,14 @@ def parse():
 
 
 def kernel_source_hash() -> str:
+    """Hash of the pass kernel's code (comments and blank lines removed), so that
+    committed counter readings are used only while they describe this code."""
+    import re
     h = hashlib.sha256()
     for f in ("ntt.hip", "field.h", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_1910_04429_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1910_04429_amd", "csrc", f)) as fh:
+            text = re.sub(r"//[^\n]*", "", fh.read())
+        h.update("\n".join(l.strip() for l in text.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
 
 

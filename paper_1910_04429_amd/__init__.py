@@ -32,7 +32,7 @@ PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENODEV = 0, 1, 2, 3, 4
 PA_MAX_N = 1 << 29
 PA_TOEPLITZ_MAX_M = 3 << 24
 PA_PROFILE_MAX = 32
-KERNEL_KINDS = {0: "ntt_pass", 1: "carry_local", 2: "carry_scan", 3: "carry_apply"}
+KERNEL_KINDS = {0: "ntt_pass", 1: "carry_local", 2: "carry_scan (reserved)", 3: "carry_apply"}
 
 
 class PAError(RuntimeError):

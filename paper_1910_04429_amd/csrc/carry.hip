@@ -15,13 +15,13 @@
 // {0..3}, f_k(c) = (s_k + c) >> 32, packed 2 bits per input in one byte;
 // composition is associative.
 //
-// Three launches, none of which waits on another workgroup: (1) every chunk of
-// digits stages its residues in LDS with coalesced loads, forms its column
-// sums and scans its threads' carry functions into the chunk's function;
-// (2) one workgroup scans the chunk functions into the carry entering each
-// chunk; (3) every chunk redoes (1), resolves its digits (and two past its end)
-// from its carry-in and writes every output word that starts inside the chunk.
-// Workgroups on different XCDs never exchange data inside a kernel.
+// Two launches, none of which waits on another workgroup: (1) every chunk of
+// digits loads its threads' residues, forms its column sums and scans its
+// threads' carry functions into the chunk's function; (2) every chunk composes
+// the functions of the chunks before it (a few thousand bytes) into its
+// carry-in, redoes (1), resolves its digits (and two past its end) and writes
+// every output word that starts inside the chunk.  Workgroups on different
+// XCDs never exchange data inside a kernel.
 #include "kernels.h"
 
 namespace pa {

@@ -9,8 +9,7 @@
 
 namespace pa {
 
-constexpr int kTileLog = 14;                 // one LDS tile: 2^14 residues, 64 KB
-constexpr int kTile = 1 << kTileLog;
+constexpr int kTileLog = 14;                 // largest LDS tile: 2^14 residues, 64 KB
 constexpr int kTileMinLog = 10;              // smallest tile of a multi-pass transform
 constexpr int kStridedMaxLog = 9;            // strided passes: <= 512 rows
 constexpr int kMaxSteps = 4;

@@ -3,8 +3,8 @@
 // The product c*x is a cyclic convolution of the two digit vectors padded to a
 // length L >= 2D - 1 (Alg. 1: fill zero, split, evaluate, pointwise multiply,
 // interpolate).  A length-L transform is a short sequence of passes; each pass
-// works on 64 KB LDS tiles (kTile residues of one prime) and reads and writes
-// its array once.
+// works on LDS tiles of at most 2^14 residues of one prime (64 KB) and reads
+// and writes its array once.
 //
 // Pass structure (decimation in frequency).  With the array seen as L/(R S)
 // blocks of R rows by S contiguous columns, a pass does a length-R transform
