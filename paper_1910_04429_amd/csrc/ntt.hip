@@ -500,6 +500,41 @@ __device__ __forceinline__ void fused_middle(uint32_t* sm, int N, const uint32_t
     }
 }
 
+// The last step of a forward contiguous pass (radix 2^R >= 4 over 2^R
+// consecutive residues, no twiddles) straight to HBM: output k of the DFT at
+// base goes to position base + bitrev(k), so each thread writes 2^R
+// consecutive residues with 16-byte stores (scaled when asked) and the tile
+// skips its last LDS round trip and the store sweep.
+template <int R, int PI>
+__device__ __forceinline__ void last_step_store(const uint32_t* sm, int N, uint32_t* out,
+                                                uint32_t limit, bool scale, uint32_t sw, uint32_t sq)
+{
+    constexpr uint32_t p = PrimeConst<PI>::p;
+    constexpr int RHO = 1 << R;
+    static_assert(RHO >= 4, "16-byte stores");
+    const int ndft = N >> R;
+    for (int q = threadIdx.x; q < ndft; q += blockDim.x) {
+        const uint32_t base = (uint32_t)q << R;
+        const uint32_t sb = swz(base);
+        uint32_t x[RHO];
+#pragma unroll
+        for (int n = 0; n < RHO; ++n)
+            x[n] = sm[sb ^ swz((uint32_t)n)];
+        dif_regs<R, PI>(x);
+        uint32_t y[RHO];
+#pragma unroll
+        for (int k = 0; k < RHO; ++k) {
+            const uint32_t v = x[bitrev_c(k, R)];
+            y[k] = scale ? fmul_shoup(v, sw, sq, p) : v;
+        }
+#pragma unroll
+        for (int v = 0; v < RHO / 4; ++v)
+            if (base + 4 * v < limit)
+                *reinterpret_cast<uint4*>(out + base + 4 * v) =
+                    make_uint4(y[4 * v], y[4 * v + 1], y[4 * v + 2], y[4 * v + 3]);
+    }
+}
+
 template <int PI>
 __device__ __forceinline__ void dispatch_fused_middle(int r, uint32_t* sm, int N, const uint32_t* chat)
 {
@@ -584,6 +619,20 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
         dispatch_fused_middle<PI>(rl, sm, N, bv.other + (size_t)PI * a.L + blk0);
         __syncthreads();
         run_pass_steps<true, PI>(a, sm, N, col0, total - 1);
+    } else if (a.f == 1 && logC == 0 && a.nsteps >= 2 && ((a.steps_code >> (4 * (a.nsteps - 1))) & 15u) >= 2) {
+        // forward contiguous pass: all steps but the last through LDS, the
+        // last straight to HBM
+        run_pass_steps<false, PI>(a, sm, N, col0, total - 1);
+        const int rl = (int)((a.steps_code >> (4 * (a.nsteps - 1))) & 15u);
+        const uint32_t lim = bv.store_limit > blk0 ? bv.store_limit - blk0 : 0u;
+        const uint32_t sw = a.scale_w[PI], sq = a.scale_q[PI];
+        if (rl == 2)
+            last_step_store<2, PI>(sm, N, data + blk0, lim, a.scale != 0, sw, sq);
+        else if (rl == 3)
+            last_step_store<3, PI>(sm, N, data + blk0, lim, a.scale != 0, sw, sq);
+        else
+            last_step_store<4, PI>(sm, N, data + blk0, lim, a.scale != 0, sw, sq);
+        return;
     } else {
         run_pass_steps<false, PI>(a, sm, N, col0, total);
     }
