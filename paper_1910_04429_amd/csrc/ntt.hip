@@ -288,8 +288,18 @@ __device__ __forceinline__ uint32_t step_exponent(const StepGeo& g, uint32_t o, 
 }
 
 // One DIF (forward) or DIT (inverse) step of radix 2^R over every DFT of the tile.
-template <int R, bool kInv, int PI>
-__device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, const Tables& tb)
+// Where a step's data comes from and goes to besides LDS: kIO = 1 reads the
+// inputs of a forward step from HBM (`in`, tile-relative), kIO = 2 writes the
+// outputs of an inverse step to HBM (`out`, positions below `limit`).
+struct GlobalIO {
+    const uint32_t* in;
+    uint32_t* out;
+    uint32_t limit;
+};
+
+template <int R, bool kInv, int PI, int kIO = 0>
+__device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, const Tables& tb,
+                                         const GlobalIO& io = GlobalIO{nullptr, nullptr, 0u})
 {
     constexpr uint32_t p = PrimeConst<PI>::p, pneg = PrimeConst<PI>::pneg;
     constexpr int RHO = 1 << R;
@@ -318,7 +328,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
         if (!kInv) {
 #pragma unroll
             for (int n = 0; n < RHO; ++n)
-                x[n] = sm[sb ^ swz(n * nstep)];
+                x[n] = (kIO == 1) ? io.in[base + n * nstep] : sm[sb ^ swz(n * nstep)];
             dif_regs<R, PI>(x);
             if (twiddle) {
                 uint32_t w = b;
@@ -347,8 +357,13 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
             }
             dit_regs<R, PI>(x);
 #pragma unroll
-            for (int n = 0; n < RHO; ++n)
-                sm[sb ^ swz(n * nstep)] = x[n];
+            for (int n = 0; n < RHO; ++n) {
+                if (kIO == 2) {
+                    if (base + n * nstep < io.limit) io.out[base + n * nstep] = x[n];
+                } else {
+                    sm[sb ^ swz(n * nstep)] = x[n];
+                }
+            }
         }
     }
 }
@@ -438,14 +453,29 @@ __device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int si, uint32_t 
     return g;
 }
 
-// Steps 0 .. count-1 of the pass (forward), or their inverse count-1 .. 0.
+// Step 0 of a contiguous pass with HBM input (forward) or output (inverse).
+template <bool kInv, int PI>
+__device__ __forceinline__ void dispatch_step_io(int r, uint32_t* sm, int N, const StepGeo& g,
+                                                 const Tables& tb, const GlobalIO& io)
+{
+    constexpr int kIO = kInv ? 2 : 1;
+    switch (r) {
+    case 1: run_step<1, kInv, PI, kIO>(sm, N, g, tb, io); break;
+    case 2: run_step<2, kInv, PI, kIO>(sm, N, g, tb, io); break;
+    case 3: run_step<3, kInv, PI, kIO>(sm, N, g, tb, io); break;
+    case 4: run_step<4, kInv, PI, kIO>(sm, N, g, tb, io); break;
+    default: break;
+    }
+}
+
+// Steps first .. count-1 of the pass (forward), or their inverse count-1 .. first.
 template <bool kInv, int PI>
 __device__ __forceinline__ void run_pass_steps(const PassArgs& a, uint32_t* sm, int N, uint32_t col0,
-                                               int count)
+                                               int count, int first = 0)
 {
     const int has3 = a.f == 3;
-    for (int k = 0; k < count; ++k) {
-        const int si = kInv ? count - 1 - k : k;
+    for (int k = first; k < count; ++k) {
+        const int si = kInv ? count - 1 - (k - first) : k;
         const StepGeo g = step_geo(a, si, col0);
         if (has3 && si == 0)
             run_step3<kInv, PI>(sm, N, g, a.tb);
@@ -572,10 +602,21 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
     const uint32_t col0 = (tile & ((1u << logCgs) - 1u)) << logC;
     const uint32_t blk0 = bg * M;             // global offset of the block
 
+    // A contiguous pass (one column) whose input is already a residue array
+    // reads its first register step straight from HBM: lanes take consecutive
+    // positions, so those loads coalesce, and the load sweep and its barrier go.
+    const int total = a.nsteps + (a.f == 3);
+    const bool contig = a.f == 1 && logC == 0 && a.nsteps >= 2;
+    const bool hbm_in = contig && bv.src == kSrcArray && a.mode != kInverse;
+    const StepGeo g0 = step_geo(a, 0, col0);
+    const int r0 = (int)(a.steps_code & 15u);
+    const GlobalIO io{data + blk0, data + blk0,
+                      bv.store_limit > blk0 ? bv.store_limit - blk0 : 0u};
+
     // Tile element (row, c) <-> global position blk0 + row S + col0 + c; moved
     // in groups of 4 consecutive columns (C >= 4) or rows (C == 1).
     const int nq = N >> 2;
-    for (int u = threadIdx.x; u < nq; u += blockDim.x) {
+    for (int u = threadIdx.x; u < nq && !hbm_in; u += blockDim.x) {
         uint32_t e, pos;
         if (logC >= 2) {
             const uint32_t row = (uint32_t)u >> (logC - 2);
@@ -603,11 +644,23 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
         }
         *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
     }
+    if (hbm_in) {
+        dispatch_step_io<false, PI>(r0, sm, N, g0, a.tb, io);
+    }
     __syncthreads();
 
-    const int total = a.nsteps + (a.f == 3);
     if (a.mode == kInverse) {
         run_pass_steps<true, PI>(a, sm, N, col0, total);
+    } else if (a.mode == kFused && hbm_in) {
+        // as below, with the first forward step read from HBM and the last
+        // inverse step (its inverse) written to HBM
+        run_pass_steps<false, PI>(a, sm, N, col0, total - 1, 1);
+        const int rl = (int)((a.steps_code >> (4 * (a.nsteps - 1))) & 15u);
+        dispatch_fused_middle<PI>(rl, sm, N, bv.other + (size_t)PI * a.L + blk0);
+        __syncthreads();
+        run_pass_steps<true, PI>(a, sm, N, col0, total - 1, 1);
+        dispatch_step_io<true, PI>(r0, sm, N, step_geo(a, 0, col0), a.tb, io);
+        return;
     } else if (a.mode == kFused) {
         // Forward steps but the last, then the last forward step, the
         // pointwise product with the pre-scaled c-hat (same layout) and the
@@ -622,7 +675,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
     } else if (a.f == 1 && logC == 0 && a.nsteps >= 2 && ((a.steps_code >> (4 * (a.nsteps - 1))) & 15u) >= 2) {
         // forward contiguous pass: all steps but the last through LDS, the
         // last straight to HBM
-        run_pass_steps<false, PI>(a, sm, N, col0, total - 1);
+        run_pass_steps<false, PI>(a, sm, N, col0, total - 1, hbm_in ? 1 : 0);
         const int rl = (int)((a.steps_code >> (4 * (a.nsteps - 1))) & 15u);
         const uint32_t lim = bv.store_limit > blk0 ? bv.store_limit - blk0 : 0u;
         const uint32_t sw = a.scale_w[PI], sq = a.scale_q[PI];
@@ -634,7 +687,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
             last_step_store<4, PI>(sm, N, data + blk0, lim, a.scale != 0, sw, sq);
         return;
     } else {
-        run_pass_steps<false, PI>(a, sm, N, col0, total);
+        run_pass_steps<false, PI>(a, sm, N, col0, total, hbm_in ? 1 : 0);
     }
 
     for (int u = threadIdx.x; u < nq; u += blockDim.x) {
