@@ -214,6 +214,39 @@ def time_single(pa, ctx, torch, blk, steps, warmup, plan=None):
     return s.elapsed_time(e) / steps, d_key, d_out
 
 
+def per_block_latency(pa, ctx, torch, blk, d_key, d_out, runs=50):
+    """Median and p99 of single blocks, each bracketed by its own events."""
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(runs)]
+    for s, e in ev:
+        s.record(stream)
+        pa.pa_hash_async(ctx, d_key, blk.seed_a, blk.seed_b, blk.n, blk.m, d_out, stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([s.elapsed_time(e) for s, e in ev])
+    return {"median_ms": round(float(np.median(ms)), 4),
+            "p99_ms": round(float(np.percentile(ms, 99)), 4), "runs": runs}
+
+
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Device-to-device copy rate (bytes read + written per second) of a
+    1 GiB buffer: the practical HBM ceiling next to the 8 TB/s spec."""
+    src = torch.zeros(mib << 17, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    gbs = 2 * src.numel() * 8 * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+    del src, dst
+    return round(gbs, 1)
+
+
 def host_to_host(pa, ctx, blk, key):
     """pa_hash from pageable host memory to host memory: the PCIe-inclusive rate
     (context only; the reported value keeps the key resident in HBM)."""
@@ -385,6 +418,7 @@ def main():
     ms_per_step, d_key, d_out = time_single(pa, ctx, torch, blk, args.steps, args.warmup, plan)
     wall = time.perf_counter() - t0
     mbps = blk.n / (ms_per_step * 1e-3) / 1e6
+    latency = per_block_latency(pa, ctx, torch, blk, d_key, d_out)
     gpu_out = d_out.cpu().numpy().view(np.uint64).copy()
 
     # per-launch HIP events, same stream, outside the timed region
@@ -408,6 +442,9 @@ def main():
                 "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": int(avg_bytes),
                 "valu_co_bound": valu_rate(avg_ms) if args.workload == "n1e8" else None}
+    copy_gbs = copy_bandwidth(torch)
+    roofline["measured_copy_gbs"] = copy_gbs
+    roofline["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
     breakdown = {k: {"ms_per_step": round(v["ms"] / args.profile_runs, 4),
                      "launches_per_step": v["launches"] // args.profile_runs}
                  for k, v in kinds.items()}
@@ -455,6 +492,7 @@ def main():
                                f"{workloads.SINGLE_BLOCKS[args.workload][2]}",
                    "n": blk.n, "m": blk.m, "transform_length": pa.pa_transform_length(blk.n),
                    "plan": plan},
+        "per_block": latency,
         "bit_exact_vs_oracle": bit_exact,
         "roofline": roofline,
         "kernels": breakdown,

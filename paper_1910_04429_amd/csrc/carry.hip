@@ -1,19 +1,22 @@
 // CRT, carry propagation, addend, mod 2^n and top-m extraction in one pass.
 //
-// After the inverse transform, position k < D holds the convolution
-// coefficient z_k = sum_{i+j=k} x_i c_j modulo each prime.  Garner's CRT turns
-// the three residues into the exact z_k < 2^93 (three 32-bit words).  Then
-// (Alg. 1, combine and carry; the addition of mpz_addmul; the mod 2^n of
-// Section 3.2.3; the export and top-r selection of Sections 3.2.4-3.2.5)
+// After the inverse transform, position K < ceil(n/64) holds the convolution
+// coefficient Z_K = sum_{i+j=K} x_i c_j of the 64-bit digits modulo each
+// prime.  Garner's CRT turns the five residues into the exact Z_K < 2^151,
+// five 32-bit words z_K[0..4] that sit at 32-bit digit positions 2K .. 2K+4 of
+// the product.  Then (Alg. 1, combine and carry; the addition of mpz_addmul;
+// the mod 2^n of Section 3.2.3; the export and top-r selection of Sections
+// 3.2.4-3.2.5), over 32-bit digit positions k,
 //
-//   s_k = lo32(z_k) + mid32(z_{k-1}) + hi32(z_{k-2}) + d_k        (s_k < 2^34)
+//   s_{2K}   = z_K[0] + z_{K-1}[2] + z_{K-2}[4] + d_{2K}              (s < 2^34)
+//   s_{2K+1} = z_K[1] + z_{K-1}[3] + d_{2K+1}
 //   V_k = (s_k + carry_k) mod 2^32,   carry_{k+1} = (s_k + carry_k) >> 32,
 //
-// with carry_0 = 0 and every carry in [0, 3].  Digits k >= D are discarded
-// (mod 2^n), the top digit is masked to n bits, and bits [n - m, n) of V are the
-// output.  The chain is a scan of carry-transfer functions f_k : {0..3} ->
-// {0..3}, f_k(c) = (s_k + c) >> 32, packed 2 bits per input in one byte;
-// composition is associative.
+// with carry_0 = 0 and every carry in [0, 3].  Digits k >= D = ceil(n/32) are
+// discarded (mod 2^n), the top digit is masked to n bits, and bits [n - m, n)
+// of V are the output.  The chain is a scan of carry-transfer functions
+// f_k : {0..3} -> {0..3}, f_k(c) = (s_k + c) >> 32, packed 2 bits per input in
+// one byte; composition is associative.
 //
 // Two launches, none of which waits on another workgroup: (1) every chunk of
 // digits loads its threads' residues, forms its column sums and scans its
@@ -75,24 +78,36 @@ __device__ __forceinline__ uint32_t addend_digit(const CarryArgs& a, uint32_t t)
     return v;
 }
 
-// Exact coefficient from its three residues (Garner).
-__device__ __forceinline__ void crt(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t& z0,
-                                    uint32_t& z1, uint32_t& z2)
+// Exact coefficient from its five residues (Garner's mixed radix, then
+// Horner in 32-bit words): z[0..4], least significant first.
+__device__ __forceinline__ void crt(const uint32_t (&r)[kNumPrimes], uint32_t (&z)[kNumPrimes])
 {
-    constexpr uint32_t p0 = kPrimes[0], p1 = kPrimes[1], p2 = kPrimes[2];
-    const uint32_t v0 = r0;
-    const uint32_t v1 = fmul_mont(fsub(r1, min(v0, v0 - p1), p1), kInvP0ModP1M, p1, kNegInv[1]);
-    const uint32_t t = fsub(r2, v0, p2);
-    const uint32_t u = fmul_mont(v1, kP0ModP2M, p2, kNegInv[2]);
-    const uint32_t v2 = fmul_mont(fsub(t, u, p2), kInvP01ModP2M, p2, kNegInv[2]);
-    const uint64_t a = (uint64_t)p0 * v1 + v0;          // < p0 p1 < 2^62
-    const uint64_t lo = kP01 * (uint64_t)v2;
-    uint64_t hi = __umul64hi(kP01, (uint64_t)v2);
-    const uint64_t zl = a + lo;
-    hi += (zl < a);
-    z0 = (uint32_t)zl;
-    z1 = (uint32_t)(zl >> 32);
-    z2 = (uint32_t)hi;
+    uint32_t v[kNumPrimes];
+#pragma unroll
+    for (int i = 0; i < kNumPrimes; ++i) {
+        const uint32_t p = kPrimes[i];
+        uint32_t t = r[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            // v_j < p_j < 2 p_i (every prime is above 2^30)
+            const uint32_t vj = (kPrimes[j] > p) ? min(v[j], v[j] - p) : v[j];
+            t = fmul_mont(fsub(t, vj, p), kGarner.inv[i][j], p, kNegInv[i]);
+        }
+        v[i] = t;
+    }
+    z[0] = v[kNumPrimes - 1];
+#pragma unroll
+    for (int i = kNumPrimes - 2; i >= 0; --i) {
+        const int words = kNumPrimes - 1 - i;     // words of the accumulator so far
+        uint64_t carry = v[i];
+#pragma unroll
+        for (int w = 0; w < words; ++w) {
+            const uint64_t t = (uint64_t)z[w] * kPrimes[i] + carry;   // < 2^63 + 2^32
+            z[w] = (uint32_t)t;
+            carry = t >> 32;
+        }
+        z[words] = (uint32_t)carry;
+    }
 }
 
 // Chunk-local digit i in [0, kChunk + 2) <-> LDS slot of the resolved digit,
@@ -124,17 +139,21 @@ __device__ __forceinline__ void bind_job(CarryArgs& a, uint32_t job)
     a.chunks = j.chunks;
 }
 
-// Residues of digit k (0 outside [0, D)).
-__device__ __forceinline__ void load_res(const CarryArgs& a, int64_t k, uint32_t& r0, uint32_t& r1,
-                                         uint32_t& r2)
+// Residues of coefficient K (0 outside [0, ceil(D / 2))).
+__device__ __forceinline__ void load_res(const CarryArgs& a, int64_t K, uint32_t (&r)[kNumPrimes])
 {
-    if (k < 0 || k >= (int64_t)a.num_digits) {
-        r0 = r1 = r2 = 0;
-        return;
-    }
-    r0 = a.res[k];
-    r1 = a.res[(size_t)a.L + k];
-    r2 = a.res[2 * (size_t)a.L + k];
+    const int64_t coeffs = (a.num_digits + 1) >> 1;
+#pragma unroll
+    for (int pi = 0; pi < kNumPrimes; ++pi)
+        r[pi] = (K < 0 || K >= coeffs) ? 0u : a.res[(size_t)pi * a.L + K];
+}
+
+// Exact coefficient K (0 outside the product's coefficients).
+__device__ __forceinline__ void load_coeff(const CarryArgs& a, int64_t K, uint32_t (&z)[kNumPrimes])
+{
+    uint32_t r[kNumPrimes];
+    load_res(a, K, r);
+    crt(r, z);
 }
 
 // kApply = false: write the chunk's carry function.  kApply = true: resolve the
@@ -158,54 +177,72 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     const uint32_t D = a.num_digits;
 
     // column sums of this thread's kPer digits (and, for the last thread, the
-    // two digits past the chunk, which it resolves with the chunk's carry-out)
+    // two digits past the chunk, which it resolves with the chunk's carry-out);
+    // its digits 2K, 2K + 1 come from coefficients K, K - 1 and K - 2
     constexpr int kExtra = 2;
+    constexpr int kCo = kPer / 2;              // coefficients per thread
     uint64_t s[kPer + kExtra];
     const int first = tid * kPer;
     const int count = kPer + (tid == kCarryThreads - 1 ? kExtra : 0);
-    const int64_t kf = k0 + first;
-    // this thread's residues, 16-byte loads when the run lies inside [0, D)
-    uint32_t r[3][kPer];
-    if (kf + kPer <= (int64_t)D) {
+    const int64_t kf = k0 + first;             // even
+    const int64_t K0 = kf >> 1;
+    const int64_t coeffs = (D + 1) >> 1;
+    // this thread's residues, vector loads when its coefficients lie inside
+    uint32_t r[kNumPrimes][kCo];
+    if (K0 + kCo <= coeffs) {
 #pragma unroll
         for (int pi = 0; pi < kNumPrimes; ++pi) {
-            const uint4* src = reinterpret_cast<const uint4*>(a.res + (size_t)pi * a.L + kf);
+            const uint32_t* src = a.res + (size_t)pi * a.L + K0;
+            if constexpr (kCo == 2) {
+                const uint2 q = *reinterpret_cast<const uint2*>(src);
+                r[pi][0] = q.x;
+                r[pi][1] = q.y;
+            } else {
 #pragma unroll
-            for (int v = 0; v < kPer / 4; ++v) {
-                const uint4 q = src[v];
-                r[pi][4 * v] = q.x;
-                r[pi][4 * v + 1] = q.y;
-                r[pi][4 * v + 2] = q.z;
-                r[pi][4 * v + 3] = q.w;
+                for (int v = 0; v < kCo / 4; ++v) {
+                    const uint4 q = reinterpret_cast<const uint4*>(src)[v];
+                    r[pi][4 * v] = q.x;
+                    r[pi][4 * v + 1] = q.y;
+                    r[pi][4 * v + 2] = q.z;
+                    r[pi][4 * v + 3] = q.w;
+                }
             }
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) load_res(a, kf + i, r[0][i], r[1][i], r[2][i]);
+        for (int i = 0; i < kCo; ++i) {
+            uint32_t q[kNumPrimes];
+            load_res(a, K0 + i, q);
+#pragma unroll
+            for (int pi = 0; pi < kNumPrimes; ++pi) r[pi][i] = q[pi];
+        }
     }
     {
-        uint32_t z0, z1, z2, q0, q1, q2;
-        load_res(a, kf - 2, q0, q1, q2);
-        crt(q0, q1, q2, z0, z1, z2);
-        uint32_t prev2_hi = z2;
-        load_res(a, kf - 1, q0, q1, q2);
-        crt(q0, q1, q2, z0, z1, z2);
-        uint32_t prev_mid = z1, prev_hi = z2;
+        uint32_t z[kNumPrimes];
+        load_coeff(a, K0 - 2, z);
+        uint32_t prev2_w4 = z[4];
+        load_coeff(a, K0 - 1, z);
+        uint32_t prev_w2 = z[2], prev_w3 = z[3], prev_w4 = z[4];
 #pragma unroll
-        for (int i = 0; i < kPer + kExtra; ++i) {
-            if (i < count) {
-                if (i < kPer) {
-                    crt(r[0][i], r[1][i], r[2][i], z0, z1, z2);
+        for (int ci = 0; ci < kCo + kExtra / 2; ++ci) {
+            if (2 * ci < count) {
+                if (ci < kCo) {
+                    uint32_t q[kNumPrimes];
+#pragma unroll
+                    for (int pi = 0; pi < kNumPrimes; ++pi) q[pi] = r[pi][ci % kCo];
+                    crt(q, z);
                 } else {
-                    load_res(a, kf + i, q0, q1, q2);
-                    crt(q0, q1, q2, z0, z1, z2);
+                    load_coeff(a, K0 + ci, z);
                 }
-                const int64_t k = kf + i;
-                const uint32_t d = (k < (int64_t)D) ? addend_digit(a, (uint32_t)k) : 0u;
-                s[i] = (k < (int64_t)D) ? (uint64_t)z0 + prev_mid + prev2_hi + d : 0ull;
-                prev2_hi = prev_hi;
-                prev_mid = z1;
-                prev_hi = z2;
+                const int64_t k = kf + 2 * ci;
+                const uint32_t d0 = (k < (int64_t)D) ? addend_digit(a, (uint32_t)k) : 0u;
+                const uint32_t d1 = (k + 1 < (int64_t)D) ? addend_digit(a, (uint32_t)(k + 1)) : 0u;
+                s[2 * ci] = (k < (int64_t)D) ? (uint64_t)z[0] + prev_w2 + prev2_w4 + d0 : 0ull;
+                s[2 * ci + 1] = (k + 1 < (int64_t)D) ? (uint64_t)z[1] + prev_w3 + d1 : 0ull;
+                prev2_w4 = prev_w4;
+                prev_w2 = z[2];
+                prev_w3 = z[3];
+                prev_w4 = z[4];
             }
         }
     }

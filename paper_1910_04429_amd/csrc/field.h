@@ -2,11 +2,11 @@
 //
 // The hash needs the low n bits of c*x (Section 2.3, the g_{c,d} definition;
 // Section 3.2.2, the large multiply done by an NTT convolution as in Alg. 1).
-// Operands are cut into 32-bit digits; the convolution coefficients
-// sum_{i+j=k} x_i c_j are below D (2^32-1)^2 < 2^88 for D <= 2^24 digits and are
-// recovered exactly by CRT from three NTTs over 31-bit primes whose product is
-// about 2^92.6.  The primes are of the form k 2^t + 1 with t >= 25, so every
-// power-of-two length up to 2^25 has a root of unity in each field.
+// Operands are cut into 64-bit digits (the key's own words); the convolution
+// coefficients sum_{i+j=k} x_i c_j are below D (2^64-1)^2 < 2^151 for D <= 2^23
+// digits and are recovered exactly by CRT from five NTTs over 31-bit primes
+// whose product is about 2^153.4.  Every prime is k 3 2^25 + 1, so every
+// length 2^k and 3 2^k up to 3 2^25 has a root of unity in each field.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,16 +14,19 @@
 
 namespace pa {
 
-constexpr int kNumPrimes = 3;
+constexpr int kNumPrimes = 5;
 constexpr int kLogMaxLen = 25;                 // min 2-adicity of the primes
 // Every transform length divides kOrder = 3 * 2^25, which divides p - 1 for
-// each prime (quotients 20, 18 and 21): one root of unity of order kOrder per
-// prime generates the twiddles of every length 2^k and 3 * 2^k.
+// each prime (quotients 20, 18, 21, 17 and 11): one root of unity of order
+// kOrder per prime generates the twiddles of every length 2^k and 3 * 2^k.
+// These five are all the primes of the form k 3 2^25 + 1 below 2^31.
 constexpr uint32_t kOrder = 3u << kLogMaxLen;
 constexpr uint32_t kPrimes[kNumPrimes] = {
     2013265921u,  // 15 * 2^27 + 1
     1811939329u,  // 27 * 2^26 + 1
     2113929217u,  // 63 * 2^25 + 1
+    1711276033u,  // 51 * 2^25 + 1
+    1107296257u,  // 33 * 2^25 + 1
 };
 
 // -p^{-1} mod 2^32 by Newton iteration (each step doubles the correct bits).
@@ -36,7 +39,8 @@ constexpr uint32_t neg_inverse_u32(uint32_t p)
 }
 
 constexpr uint32_t kNegInv[kNumPrimes] = {
-    neg_inverse_u32(kPrimes[0]), neg_inverse_u32(kPrimes[1]), neg_inverse_u32(kPrimes[2])};
+    neg_inverse_u32(kPrimes[0]), neg_inverse_u32(kPrimes[1]), neg_inverse_u32(kPrimes[2]),
+    neg_inverse_u32(kPrimes[3]), neg_inverse_u32(kPrimes[4])};
 
 constexpr uint64_t pow_mod(uint64_t b, uint64_t e, uint64_t p)
 {
@@ -85,30 +89,47 @@ constexpr uint32_t order_root(uint64_t p)
 }
 
 constexpr uint32_t kRoot[kNumPrimes] = {order_root(kPrimes[0]), order_root(kPrimes[1]),
-                                        order_root(kPrimes[2])};
-
-static_assert(pow_mod(kRoot[0], kOrder / 2, kPrimes[0]) == kPrimes[0] - 1 &&
-                  pow_mod(kRoot[1], kOrder / 3, kPrimes[1]) != 1 &&
-                  pow_mod(kRoot[2], kOrder, kPrimes[2]) == 1,
-              "root of order 3 * 2^25");
+                                        order_root(kPrimes[2]), order_root(kPrimes[3]),
+                                        order_root(kPrimes[4])};
 
 // Shoup quotient floor(w 2^32 / p) of a constant w < p.
 constexpr uint32_t shoup_quotient(uint64_t w, uint64_t p) { return (uint32_t)((w << 32) / p); }
 
-// Garner CRT constants for (p0, p1, p2).
-constexpr uint64_t kP01 = (uint64_t)kPrimes[0] * kPrimes[1];
-constexpr uint32_t kInvP0ModP1M = to_mont(inv_mod(kPrimes[0] % kPrimes[1], kPrimes[1]), kPrimes[1]);
-constexpr uint32_t kP0ModP2M = to_mont(kPrimes[0] % kPrimes[2], kPrimes[2]);
-constexpr uint32_t kInvP01ModP2M = to_mont(inv_mod(kP01 % kPrimes[2], kPrimes[2]), kPrimes[2]);
+// Garner's mixed-radix CRT: with v_0 = r_0 and
+//   v_i = (...((r_i - v_0) p_0^{-1} - v_1) p_1^{-1} ... - v_{i-1}) p_{i-1}^{-1}  mod p_i,
+// the coefficient is v_0 + p_0 (v_1 + p_1 (v_2 + p_2 (v_3 + p_3 v_4))).
+// kGarner[i][j] is p_j^{-1} mod p_i in Montgomery form (j < i).
+struct GarnerTable {
+    uint32_t inv[kNumPrimes][kNumPrimes];
+};
+constexpr GarnerTable make_garner()
+{
+    GarnerTable t{};
+    for (int i = 0; i < kNumPrimes; ++i)
+        for (int j = 0; j < i; ++j)
+            t.inv[i][j] = to_mont(inv_mod(kPrimes[j] % kPrimes[i], kPrimes[i]), kPrimes[i]);
+    return t;
+}
+constexpr GarnerTable kGarner = make_garner();
 
-static_assert(kPrimes[0] > kPrimes[1] && kPrimes[0] < 2 * (uint64_t)kPrimes[1],
-              "Garner step assumes p1 < p0 < 2 p1");
-static_assert(kPrimes[0] < kPrimes[2] && kPrimes[1] < kPrimes[2],
-              "Garner step assumes p0, p1 < p2");
-static_assert((uint32_t)(kNegInv[0] * kPrimes[0]) == 0xFFFFFFFFu, "Montgomery constant");
-static_assert((kPrimes[0] - 1) % kOrder == 0 && (kPrimes[1] - 1) % kOrder == 0 &&
-                  (kPrimes[2] - 1) % kOrder == 0,
-              "every prime has roots of unity of order 3 * 2^25");
+constexpr bool primes_ok()
+{
+    for (int i = 0; i < kNumPrimes; ++i) {
+        const uint64_t p = kPrimes[i];
+        // odd, 2^30 < p < 2^31: a residue of any of the primes is below 2 p
+        if (p % 2 == 0 || p <= (1ull << 30) || p >= (1ull << 31)) return false;
+        if ((p - 1) % kOrder != 0) return false;
+        if ((uint32_t)(kNegInv[i] * (uint32_t)p) != 0xFFFFFFFFu) return false;
+        // the root has order exactly 3 * 2^25
+        if (pow_mod(kRoot[i], kOrder, p) != 1 || pow_mod(kRoot[i], kOrder / 2, p) == 1 ||
+            pow_mod(kRoot[i], kOrder / 3, p) == 1)
+            return false;
+        for (int j = 0; j < i; ++j)
+            if (kPrimes[j] == p) return false;
+    }
+    return true;
+}
+static_assert(primes_ok(), "five distinct primes in (2^30, 2^31) with roots of order 3 * 2^25");
 
 // ---------------------------------------------------------------------------
 // Canonical residues in [0, p), p < 2^31.
@@ -153,9 +174,14 @@ __device__ __forceinline__ uint32_t fmul_mont_lazy(uint32_t a, uint32_t b, uint3
     return (uint32_t)((t + (uint64_t)m * p) >> 32);
 }
 
-// v mod p for any 32-bit v (v < 3p for these primes).
+// v mod p for any 32-bit v: p > 2^30, so v < 4p and three conditional
+// subtractions suffice (two when 3p > 2^32 - 1).
 __device__ __forceinline__ uint32_t freduce32(uint32_t v, uint32_t p)
 {
+    if (3ull * p <= 0xFFFFFFFFull) {
+        v = min(v, v - 2 * p);
+        return min(v, v - p);
+    }
     v = min(v, v - p);
     return min(v, v - p);
 }

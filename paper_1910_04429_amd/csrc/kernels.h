@@ -27,8 +27,8 @@ struct Tables {
 
 enum Source : int {
     kSrcArray = 0,   // residues already in `data`
-    kSrcDigits = 1,  // 32-bit digits of an n-bit operand in memory
-    kSrcSeed = 2,    // digits of the SplitMix64 stream of `seed`, bit 0 forced to 1
+    kSrcDigits = 1,  // 64-bit digits (the words) of an n-bit operand in memory
+    kSrcSeed = 2,    // words of the SplitMix64 stream of `seed`, bit 0 forced to 1
     kSrcBits = 3,    // element e = bit bit_off + e of `digits` for e < n, else 0
 };
 
@@ -70,7 +70,7 @@ enum PassMode : int {
 struct PassArgs {
     uint32_t* data;            // [kNumPrimes][L]
     const uint32_t* other;     // kFused: pre-scaled c-hat, same layout
-    const uint32_t* digits;    // kSrcDigits: ceil(n/32) 32-bit digits
+    const uint32_t* digits;    // kSrcDigits: the operand's words as ceil(n/32) 32-bit halves
     uint64_t seed;             // kSrcSeed
     uint64_t n;                // operand bits (sources only); kSrcBits: elements
     uint64_t bit_off;          // kSrcBits: bit of `digits` that element 0 takes
@@ -97,7 +97,8 @@ struct PassArgs {
     // batch mode (jobs != null): per-block fields come from jobs[blockIdx.z]
     const JobDesc* jobs;
     int role;
-    int limit_to_digits;       // store only positions < ceil(D / 4) * 4
+    int limit_to_digits;       // store only the product's coefficients: positions
+                               // below ceil(ceil(D / 2) / 4) * 4
 };
 
 // CRT, carry propagation, addend and bit extraction over the product.

@@ -1,8 +1,8 @@
-// Multi-pass number-theoretic transform over the three primes of field.h.
+// Multi-pass number-theoretic transform over the five primes of field.h.
 //
-// The product c*x is a cyclic convolution of the two digit vectors padded to a
-// length L >= 2D - 1 (Alg. 1: fill zero, split, evaluate, pointwise multiply,
-// interpolate).  A length-L transform is a short sequence of passes; each pass
+// The product c*x is a cyclic convolution of the two vectors of 64-bit digits
+// padded to a length L >= 2D - 1 (Alg. 1: fill zero, split, evaluate,
+// pointwise multiply, interpolate).  A length-L transform is a short sequence of passes; each pass
 // works on LDS tiles of at most 2^14 residues of one prime (64 KB) and reads
 // and writes its array once.
 //
@@ -67,7 +67,19 @@ struct PrimeConst {
     static constexpr uint64_t w64inv = pow_mod(w64, kPrimes[PI] - 2, kPrimes[PI]);
     static constexpr uint64_t w3 = pow_mod(kRoot[PI], kOrder / 3, kPrimes[PI]);
     static constexpr uint64_t w3sq = w3 * w3 % kPrimes[PI];
+    // 2^32 mod p and its Shoup quotient: a 64-bit digit hi 2^32 + lo is
+    // hi (2^32 mod p) + lo mod p
+    static constexpr uint32_t r32 = (uint32_t)((1ull << 32) % kPrimes[PI]);
+    static constexpr uint32_t r32q = shoup_quotient(r32, kPrimes[PI]);
 };
+
+// A 64-bit digit (lo, hi) reduced mod prime PI.
+template <int PI>
+__device__ __forceinline__ uint32_t reduce64(uint32_t lo, uint32_t hi)
+{
+    constexpr uint32_t p = PrimeConst<PI>::p;
+    return fadd(freduce32(lo, p), fmul_shoup(hi, PrimeConst<PI>::r32, PrimeConst<PI>::r32q, p), p);
+}
 
 // omega_64^e (kInv: omega_64^{-e}) and its Shoup quotient, e < 32.
 template <int PI, bool kInv>
@@ -126,7 +138,7 @@ __device__ __forceinline__ BlockView block_view(const PassArgs& a)
             }
         }
         if (a.limit_to_digits)
-            v.store_limit = (j.num_digits + 3u) & ~3u;
+            v.store_limit = (((j.num_digits + 1u) >> 1) + 3u) & ~3u;
     } else if (a.dual && blockIdx.z == 1) {
         v.data = const_cast<uint32_t*>(a.other);
         v.src = kSrcDigits;
@@ -134,48 +146,47 @@ __device__ __forceinline__ BlockView block_view(const PassArgs& a)
     return v;
 }
 
-// Digits pos .. pos + 3 (pos a multiple of 4) of the operand described by the
-// block's source, 0 beyond the top digit: one 16-byte load of key digits, or
-// two SplitMix64 words of a seeded multiplier (bit 0 forced to 1, eq. (6)).
-__device__ __forceinline__ uint4 source_quad(const BlockView& a, uint32_t pos)
+// 64-bit digits pos .. pos + 3 (pos a multiple of 4) of the operand described
+// by the block's source as eight 32-bit halves, low half first, 0 beyond bit
+// n: two 16-byte loads of key words, or four SplitMix64 words of a seeded
+// multiplier (bit 0 forced to 1, eq. (6)).
+__device__ __forceinline__ void source_quad(const BlockView& a, uint32_t pos, uint32_t (&v)[8])
 {
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    const uint32_t D = a.num_digits;
-    if (pos >= D)
-        return v;
+    const uint32_t D = a.num_digits;          // 32-bit digits of the operand
+    const uint32_t d0 = 2 * pos;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = 0u;
+    if (d0 >= D)
+        return;
     if (a.src == kSrcDigits) {
-        if (pos + 4 <= D && (reinterpret_cast<uintptr_t>(a.digits) & 15u) == 0) {
-            v = *reinterpret_cast<const uint4*>(a.digits + pos);
+        if (d0 + 8 <= D && (reinterpret_cast<uintptr_t>(a.digits) & 15u) == 0) {
+            const uint4 q0 = *reinterpret_cast<const uint4*>(a.digits + d0);
+            const uint4 q1 = *reinterpret_cast<const uint4*>(a.digits + d0 + 4);
+            v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w;
+            v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
         } else {
-            v.x = a.digits[pos];
-            if (pos + 1 < D) v.y = a.digits[pos + 1];
-            if (pos + 2 < D) v.z = a.digits[pos + 2];
-            if (pos + 3 < D) v.w = a.digits[pos + 3];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (d0 + i < D) v[i] = a.digits[d0 + i];
         }
     } else {
-        const uint64_t w0 = splitmix64(a.seed, pos >> 1);
-        v.x = (uint32_t)w0 | (pos == 0 ? 1u : 0u);
-        v.y = (uint32_t)(w0 >> 32);
-        if (pos + 2 < D) {
-            const uint64_t w1 = splitmix64(a.seed, (pos >> 1) + 1);
-            v.z = (uint32_t)w1;
-            v.w = (uint32_t)(w1 >> 32);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (d0 + 2 * e < D) {
+                const uint64_t w = splitmix64(a.seed, pos + e);
+                v[2 * e] = (uint32_t)w | ((pos + e == 0) ? 1u : 0u);
+                v[2 * e + 1] = (d0 + 2 * e + 1 < D) ? (uint32_t)(w >> 32) : 0u;
+            }
         }
-        if (pos + 1 >= D) v.y = 0;
-        if (pos + 3 >= D) v.w = 0;
     }
-    // bits past n in the top digit
+    // bits past n in the top 32-bit digit
     const uint32_t top = (uint32_t)(a.n & 31);
-    if (top && D - 1 - pos < 4u) {
+    if (top) {
         const uint32_t mask = (1u << top) - 1u;
-        switch (D - 1 - pos) {
-        case 0: v.x &= mask; break;
-        case 1: v.y &= mask; break;
-        case 2: v.z &= mask; break;
-        default: v.w &= mask; break;
-        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (d0 + i == D - 1) v[i] &= mask;
     }
-    return v;
 }
 
 // Element t of a bit source: bit bit_off + t of the 32-bit word array, 0 for t >= n.
@@ -636,11 +647,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
             v.z = source_bit(bv, pos + 2);
             v.w = source_bit(bv, pos + 3);
         } else {
-            v = source_quad(bv, pos);
-            v.x = freduce32(v.x, p);
-            v.y = freduce32(v.y, p);
-            v.z = freduce32(v.z, p);
-            v.w = freduce32(v.w, p);
+            uint32_t h[8];
+            source_quad(bv, pos, h);
+            v.x = reduce64<PI>(h[0], h[1]);
+            v.y = reduce64<PI>(h[2], h[3]);
+            v.z = reduce64<PI>(h[4], h[5]);
+            v.w = reduce64<PI>(h[6], h[7]);
         }
         *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
     }
@@ -720,7 +732,9 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
     switch (blockIdx.y) {
     case 0: pass_tile<0>(a, sm); break;
     case 1: pass_tile<1>(a, sm); break;
-    default: pass_tile<2>(a, sm); break;
+    case 2: pass_tile<2>(a, sm); break;
+    case 3: pass_tile<3>(a, sm); break;
+    default: pass_tile<4>(a, sm); break;
     }
 }
 

@@ -50,10 +50,12 @@ int fail(pa_ctx* ctx, int code, const char* what, hipError_t e = hipSuccess)
 
 uint64_t words_of(uint64_t bits) { return (bits + 63) / 64; }
 uint64_t digits_of(uint64_t bits) { return (bits + 31) / 32; }
+// Transform elements of an n-bit operand: its 64-bit digits.
+uint64_t coeffs_of(uint64_t bits) { return (bits + 63) / 64; }
 
-// Transform length for a block of n bits: the smallest L >= 2D - 1 among 2^l
-// and, for long transforms, 3 * 2^(l-2) (a quarter shorter when it fits, as
-// for n = 10^8: 2D - 1 = 6 249 999 <= 3 * 2^21).
+// Transform length for a block of n bits cut into D = ceil(n / 64) digits:
+// the smallest L >= 2D - 1 among 2^l and, for long transforms, 3 * 2^(l-2) (a
+// quarter shorter when it fits, as for n = 10^8: 2D - 1 = 3 124 999 <= 3 * 2^20).
 #ifndef PA_MIXED_RADIX_MIN_LOG
 #define PA_MIXED_RADIX_MIN_LOG 18
 #endif
@@ -75,7 +77,7 @@ Len len_for(uint64_t need)
     return {1, l};
 }
 
-Len plan_len(uint64_t n) { return len_for(2 * digits_of(n) - 1); }
+Len plan_len(uint64_t n) { return len_for(2 * coeffs_of(n) - 1); }
 
 uint64_t len_of(uint64_t n) { return plan_len(n).L(); }
 
@@ -330,7 +332,7 @@ bool plan_for(const pa_ctx* ctx, Len len, Plan* pl)
 }
 
 // Operands of one block.  In batch mode the kernels read them from the job
-// table instead, and `key_bytes` / `digits` / `out_bytes` are batch totals
+// table instead, and `key_bytes` / `coeffs` / `out_bytes` are batch totals
 // used only for the profile's byte counts.
 struct Work {
     const uint32_t* key = nullptr;     // key digits
@@ -346,7 +348,7 @@ struct Work {
     unsigned batch = 1;
     uint32_t chunks = 0;               // grid width of the carry kernels
     int per = 4;                       // carry digits per thread
-    uint64_t key_bytes = 0, digits = 0, out_bytes = 0;
+    uint64_t key_bytes = 0, coeffs = 0, out_bytes = 0;
     bool have_chat = false;            // A already holds c-hat (cached multiplier)
     bool only_chat = false;            // transform c into A and stop
 };
@@ -378,7 +380,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     const unsigned batch = w.batch;
     const uint64_t L = pl.L;
     const uint64_t arr = batch * kNumPrimes * 4ull * L;    // residue arrays, all blocks
-    const uint64_t outD = kNumPrimes * 4ull * w.digits;    // product coefficients kept
+    const uint64_t outD = kNumPrimes * 4ull * w.coeffs;    // product coefficients kept
     const int P = pl.P;
 
     PassArgs base{};
@@ -389,7 +391,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     base.store_limit = (uint32_t)L;
     base.jobs = w.jobs;
     auto geometry = [&](PassArgs& a, int i) { pass_geometry(a, pl, i); };
-    const uint32_t limit = (uint32_t)((digits_of(w.n) + 3) & ~3ull);
+    const uint32_t limit = (uint32_t)((coeffs_of(w.n) + 3) & ~3ull);
 
     // The first passes of c and of x share their geometry and are independent:
     // one launch runs both (grid.z = 2), so each fills the other's last wave.
@@ -515,7 +517,7 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     w.chunks = chunks_of(digits_of(n));
     w.per = carry_digits_per_thread((uint32_t)digits_of(n));
     w.key_bytes = (n + 7) / 8;
-    w.digits = digits_of(n);
+    w.coeffs = coeffs_of(n);
     w.out_bytes = words_of(m) * 8;
     return enqueue_plan(ctx, pl, w, stream, rec);
 }
@@ -558,7 +560,7 @@ int enqueue_block(pa_ctx* ctx, const BlockBufs& b, hipStream_t stream)
     w.chunks = chunks_of(digits_of(b.n));
     w.per = carry_digits_per_thread((uint32_t)digits_of(b.n));
     w.key_bytes = (b.n + 7) / 8;
-    w.digits = digits_of(b.n);
+    w.coeffs = coeffs_of(b.n);
     w.out_bytes = words_of(b.m) * 8;
     return enqueue_plan(ctx, pl, w, stream);
 }
@@ -574,7 +576,7 @@ struct pa_batch {
         uint32_t first = 0, count = 0;   // range in the job table
         uint32_t chunks = 0;             // widest carry grid of the group
         int per = 4;
-        uint64_t key_bytes = 0, digits = 0, out_bytes = 0;
+        uint64_t key_bytes = 0, coeffs = 0, out_bytes = 0;
     };
     std::vector<Group> groups;
     JobDesc* d_jobs = nullptr;
@@ -611,7 +613,7 @@ int enqueue_batch(pa_batch* b, hipStream_t stream)
         w.chunks = g.chunks;
         w.per = g.per;
         w.key_bytes = g.key_bytes;
-        w.digits = g.digits;
+        w.coeffs = g.coeffs;
         w.out_bytes = g.out_bytes;
         int rc = enqueue_plan(ctx, g.plan, w, st);
         if (rc) return rc;
@@ -1068,7 +1070,7 @@ int pa_mul_create(pa_ctx* ctx, uint64_t seed_a, const uint64_t* d_c, uint64_t n,
     w.A = mh->A;
     w.only_chat = true;
     w.key_bytes = (n + 7) / 8;
-    w.digits = digits_of(n);
+    w.coeffs = coeffs_of(n);
     rc = enqueue_plan(ctx, pl, w, (hipStream_t)stream);
     if (rc) {
         (void)hipFree(mh->A);
@@ -1103,7 +1105,7 @@ int pa_hash_mul_async(pa_ctx* ctx, const pa_mul* mh, const uint64_t* d_key, uint
     w.chunks = chunks_of(digits_of(n));
     w.per = carry_digits_per_thread((uint32_t)digits_of(n));
     w.key_bytes = (n + 7) / 8;
-    w.digits = digits_of(n);
+    w.coeffs = coeffs_of(n);
     w.out_bytes = words_of(m) * 8;
     w.have_chat = true;
     return enqueue_plan(ctx, pl, w, (hipStream_t)stream);
@@ -1203,7 +1205,7 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
             d.out = j.out;
             g.chunks = std::max(g.chunks, d.chunks);
             g.key_bytes += (j.n + 7) / 8;
-            g.digits += D;
+            g.coeffs += coeffs_of(j.n);
             g.out_bytes += words_of(j.m) * 8;
             offA[k] = bytes;
             bytes += 2 * align256(kNumPrimes * 4ull * L);

@@ -35,15 +35,15 @@ def test_library_exports_every_declared_symbol():
 def test_host_helpers():
     import paper_1910_04429_amd as pa
     # L = smallest 2^k (k >= 6) or, from 2^18 on, 3 * 2^k with L >= 2D - 1,
-    # D = ceil(n / 32)
+    # D = ceil(n / 64) digits of 64 bits
     assert pa.pa_transform_length(1) == 64
-    assert pa.pa_transform_length(1_000_000) == 1 << 16        # 2D - 1 = 62499
-    assert pa.pa_transform_length(10_000_000) == 3 << 18       # 624999
-    assert pa.pa_transform_length(100_000_000) == 3 << 21      # 6249999
-    assert pa.pa_transform_length(pa.PA_MAX_N) == 1 << 25
+    assert pa.pa_transform_length(1_000_000) == 1 << 15        # 2D - 1 = 31249
+    assert pa.pa_transform_length(10_000_000) == 3 << 17       # 312499
+    assert pa.pa_transform_length(100_000_000) == 3 << 20      # 3124999
+    assert pa.pa_transform_length(pa.PA_MAX_N) == 1 << 24      # 2^24 - 1
     assert pa.pa_transform_length(pa.PA_MAX_N + 1) == 0
     assert pa.pa_transform_length(0) == 0
-    assert pa.pa_workspace_bytes(100_000_000) >= 2 * 3 * 4 * (3 << 21)
+    assert pa.pa_workspace_bytes(100_000_000) >= 2 * 5 * 4 * (3 << 20)
     assert pa.pa_strerror(pa.PA_EINVAL) == "invalid argument"
 
 
