@@ -175,6 +175,11 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     const uint32_t chunk = blockIdx.x;
     const int64_t k0 = (int64_t)chunk * kChunk;
     const uint32_t D = a.num_digits;
+    // A chunk below bit n - m writes no output word (none starts in it): its
+    // digits reach the output only through its carry function, which the local
+    // kernel has written.
+    if (kApply && (uint64_t)(k0 + kChunk) * 32 <= a.n - a.m)
+        return;
 
     // column sums of this thread's kPer digits (and, for the last thread, the
     // two digits past the chunk, which it resolves with the chunk's carry-out);
@@ -217,32 +222,63 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
             for (int pi = 0; pi < kNumPrimes; ++pi) r[pi][i] = q[pi];
         }
     }
+    // Exact coefficients of this thread.  The high words of the two before its
+    // first come from the previous thread through LDS; for thread 0 they are
+    // the chunk's boundary coefficients, and the last thread's two extra digits
+    // need the coefficient past the chunk: lane 0 of waves 1, 2 and 3 computes
+    // one each, so that no wave runs more than one CRT beyond its own.
+    uint32_t z[kCo][kNumPrimes];
+#pragma unroll
+    for (int ci = 0; ci < kCo; ++ci) {
+        uint32_t q[kNumPrimes];
+#pragma unroll
+        for (int pi = 0; pi < kNumPrimes; ++pi) q[pi] = r[pi][ci];
+        crt(q, z[ci]);
+    }
+    // hw[t + 1] = words 2, 3, 4 of thread t's last coefficient and word 4 of
+    // the one before it; hw[0] the same for the two coefficients before the chunk
+    __shared__ uint4 hw[kCarryThreads + 1];
+    __shared__ uint32_t tail[2];
+    static_assert(kCarryThreads == 256, "boundary coefficients go to waves 1, 2 and 3");
+    hw[tid + 1] = make_uint4(z[kCo - 1][2], z[kCo - 1][3], z[kCo - 1][4], z[kCo - 2][4]);
     {
-        uint32_t z[kNumPrimes];
-        load_coeff(a, K0 - 2, z);
-        uint32_t prev2_w4 = z[4];
-        load_coeff(a, K0 - 1, z);
-        uint32_t prev_w2 = z[2], prev_w3 = z[3], prev_w4 = z[4];
+        const int64_t Kc = k0 >> 1;            // first coefficient of the chunk
+        uint32_t q[kNumPrimes];
+        if (tid == 64) {
+            load_coeff(a, Kc - 1, q);
+            hw[0].x = q[2];
+            hw[0].y = q[3];
+            hw[0].z = q[4];
+        } else if (tid == 128) {
+            load_coeff(a, Kc - 2, q);
+            hw[0].w = q[4];
+        } else if (tid == 192) {
+            load_coeff(a, Kc + kChunk / 2, q);
+            tail[0] = q[0];
+            tail[1] = q[1];
+        }
+    }
+    __syncthreads();
+    {
+        const uint4 h = hw[tid];
+        uint32_t prev_w2 = h.x, prev_w3 = h.y, prev_w4 = h.z, prev2_w4 = h.w;
 #pragma unroll
         for (int ci = 0; ci < kCo + kExtra / 2; ++ci) {
             if (2 * ci < count) {
-                if (ci < kCo) {
-                    uint32_t q[kNumPrimes];
-#pragma unroll
-                    for (int pi = 0; pi < kNumPrimes; ++pi) q[pi] = r[pi][ci % kCo];
-                    crt(q, z);
-                } else {
-                    load_coeff(a, K0 + ci, z);
-                }
+                const bool own = ci < kCo;
+                const uint32_t w0 = own ? z[ci % kCo][0] : tail[0];
+                const uint32_t w1 = own ? z[ci % kCo][1] : tail[1];
                 const int64_t k = kf + 2 * ci;
                 const uint32_t d0 = (k < (int64_t)D) ? addend_digit(a, (uint32_t)k) : 0u;
                 const uint32_t d1 = (k + 1 < (int64_t)D) ? addend_digit(a, (uint32_t)(k + 1)) : 0u;
-                s[2 * ci] = (k < (int64_t)D) ? (uint64_t)z[0] + prev_w2 + prev2_w4 + d0 : 0ull;
-                s[2 * ci + 1] = (k + 1 < (int64_t)D) ? (uint64_t)z[1] + prev_w3 + d1 : 0ull;
-                prev2_w4 = prev_w4;
-                prev_w2 = z[2];
-                prev_w3 = z[3];
-                prev_w4 = z[4];
+                s[2 * ci] = (k < (int64_t)D) ? (uint64_t)w0 + prev_w2 + prev2_w4 + d0 : 0ull;
+                s[2 * ci + 1] = (k + 1 < (int64_t)D) ? (uint64_t)w1 + prev_w3 + d1 : 0ull;
+                if (own) {
+                    prev2_w4 = prev_w4;
+                    prev_w2 = z[ci % kCo][2];
+                    prev_w3 = z[ci % kCo][3];
+                    prev_w4 = z[ci % kCo][4];
+                }
             }
         }
     }
