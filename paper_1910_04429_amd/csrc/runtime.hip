@@ -81,6 +81,18 @@ Len plan_len(uint64_t n) { return len_for(2 * coeffs_of(n) - 1); }
 
 uint64_t len_of(uint64_t n) { return plan_len(n).L(); }
 
+// Coefficients the carry apply kernel reads for an n-bit block with an m-bit
+// output: those of the chunks that hold an output word's first bit (chunks
+// wholly below bit n - m return at once).
+uint64_t window_coeffs(uint64_t n, uint64_t m)
+{
+    const uint64_t D = (n + 31) / 32;
+    const uint64_t chunk = (uint64_t)kCarryThreads * carry_digits_per_thread((uint32_t)D);
+    const uint64_t skipped = ((n - m) / 32 / chunk) * chunk / 2;
+    const uint64_t total = (n + 63) / 64;
+    return skipped < total ? total - skipped : 0;
+}
+
 uint32_t chunks_of(uint64_t D)
 {
     const uint64_t chunk = (uint64_t)kCarryThreads * carry_digits_per_thread((uint32_t)D);
@@ -349,6 +361,7 @@ struct Work {
     uint32_t chunks = 0;               // grid width of the carry kernels
     int per = 4;                       // carry digits per thread
     uint64_t key_bytes = 0, coeffs = 0, out_bytes = 0;
+    uint64_t window = 0;               // coefficients the apply kernel reads
     bool have_chat = false;            // A already holds c-hat (cached multiplier)
     bool only_chat = false;            // transform c into A and stop
 };
@@ -487,7 +500,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     ca.jobs = w.jobs;
     const uint64_t chunk_bytes = 4ull * w.chunks * batch;
     PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + chunk_bytes, launch_carry_local(ca, stream, batch, ev_));
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, outD + chunk_bytes + w.out_bytes,
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, kNumPrimes * 4ull * w.window + chunk_bytes + w.out_bytes,
               launch_carry_apply(ca, stream, batch, ev_));
     return PA_OK;
 }
@@ -518,6 +531,7 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     w.per = carry_digits_per_thread((uint32_t)digits_of(n));
     w.key_bytes = (n + 7) / 8;
     w.coeffs = coeffs_of(n);
+    w.window = window_coeffs(n, m);
     w.out_bytes = words_of(m) * 8;
     return enqueue_plan(ctx, pl, w, stream, rec);
 }
@@ -561,6 +575,7 @@ int enqueue_block(pa_ctx* ctx, const BlockBufs& b, hipStream_t stream)
     w.per = carry_digits_per_thread((uint32_t)digits_of(b.n));
     w.key_bytes = (b.n + 7) / 8;
     w.coeffs = coeffs_of(b.n);
+    w.window = window_coeffs(b.n, b.m);
     w.out_bytes = words_of(b.m) * 8;
     return enqueue_plan(ctx, pl, w, stream);
 }
@@ -576,7 +591,7 @@ struct pa_batch {
         uint32_t first = 0, count = 0;   // range in the job table
         uint32_t chunks = 0;             // widest carry grid of the group
         int per = 4;
-        uint64_t key_bytes = 0, coeffs = 0, out_bytes = 0;
+        uint64_t key_bytes = 0, coeffs = 0, out_bytes = 0, window = 0;
     };
     std::vector<Group> groups;
     JobDesc* d_jobs = nullptr;
@@ -614,6 +629,7 @@ int enqueue_batch(pa_batch* b, hipStream_t stream)
         w.per = g.per;
         w.key_bytes = g.key_bytes;
         w.coeffs = g.coeffs;
+        w.window = g.window;
         w.out_bytes = g.out_bytes;
         int rc = enqueue_plan(ctx, g.plan, w, st);
         if (rc) return rc;
@@ -1106,6 +1122,7 @@ int pa_hash_mul_async(pa_ctx* ctx, const pa_mul* mh, const uint64_t* d_key, uint
     w.per = carry_digits_per_thread((uint32_t)digits_of(n));
     w.key_bytes = (n + 7) / 8;
     w.coeffs = coeffs_of(n);
+    w.window = window_coeffs(n, m);
     w.out_bytes = words_of(m) * 8;
     w.have_chat = true;
     return enqueue_plan(ctx, pl, w, (hipStream_t)stream);
@@ -1206,6 +1223,7 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
             g.chunks = std::max(g.chunks, d.chunks);
             g.key_bytes += (j.n + 7) / 8;
             g.coeffs += coeffs_of(j.n);
+            g.window += window_coeffs(j.n, j.m);
             g.out_bytes += words_of(j.m) * 8;
             offA[k] = bytes;
             bytes += 2 * align256(kNumPrimes * 4ull * L);
