@@ -295,7 +295,10 @@ int pa_plan_set(pa_ctx *ctx, uint64_t n, const pa_plan *p);
  * Autotune: time one hash of a seeded n-bit block (m = n / 2) reps times with
  * every candidate geometry of that transform length on the device, keep the
  * fastest for ctx (as pa_plan_set would) and return it in *best (may be NULL).
- * Allocates two temporary device buffers; synchronises the context's stream.
+ * It first runs the default geometry for about 30 ms, so that the clocks have
+ * risen, then sweeps the candidates twice (the second time in reverse order)
+ * and keeps each one's faster time.  Allocates two temporary device buffers;
+ * synchronises the context's stream.
  */
 int pa_tune(pa_ctx *ctx, uint64_t n, int reps, pa_plan *best);
 
