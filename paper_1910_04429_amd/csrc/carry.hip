@@ -1,15 +1,15 @@
 // CRT, carry propagation, addend, mod 2^n and top-m extraction in one pass.
 //
-// After the inverse transform, position K < ceil(n/64) holds the convolution
-// coefficient Z_K = sum_{i+j=K} x_i c_j of the 64-bit digits modulo each
-// prime.  Garner's CRT turns the five residues into the exact Z_K < 2^151,
-// five 32-bit words z_K[0..4] that sit at 32-bit digit positions 2K .. 2K+4 of
-// the product.  Then (Alg. 1, combine and carry; the addition of mpz_addmul;
-// the mod 2^n of Section 3.2.3; the export and top-r selection of Sections
-// 3.2.4-3.2.5), over 32-bit digit positions k,
+// After the inverse transform, position K < ceil(n / 32 W) holds the
+// convolution coefficient Z_K = sum_{i+j=K} x_i c_j of the digits of W 32-bit
+// words modulo each of the P = 2 W + 1 primes.  Garner's CRT turns the
+// residues into the exact Z_K (below 2^{64 W + 23}), P 32-bit words z_K[0..P)
+// that sit at 32-bit digit positions W K .. W K + 2 W of the product.  Then
+// (Alg. 1, combine and carry; the addition of mpz_addmul; the mod 2^n of
+// Section 3.2.3; the export and top-r selection of Sections 3.2.4-3.2.5), over
+// 32-bit digit positions k = W K + r, r < W,
 //
-//   s_{2K}   = z_K[0] + z_{K-1}[2] + z_{K-2}[4] + d_{2K}              (s < 2^34)
-//   s_{2K+1} = z_K[1] + z_{K-1}[3] + d_{2K+1}
+//   s_k = z_K[r] + z_{K-1}[r + W] + (r == 0 ? z_{K-2}[2 W] : 0) + d_k   (s < 2^34)
 //   V_k = (s_k + carry_k) mod 2^32,   carry_{k+1} = (s_k + carry_k) >> 32,
 //
 // with carry_0 = 0 and every carry in [0, 3].  Digits k >= D = ceil(n/32) are
@@ -78,13 +78,14 @@ __device__ __forceinline__ uint32_t addend_digit(const CarryArgs& a, uint32_t t)
     return v;
 }
 
-// Exact coefficient from its five residues (Garner's mixed radix, then
-// Horner in 32-bit words): z[0..4], least significant first.
-__device__ __forceinline__ void crt(const uint32_t (&r)[kNumPrimes], uint32_t (&z)[kNumPrimes])
+// Exact coefficient from its residues over the first NP primes (Garner's mixed
+// radix, then Horner in 32-bit words): z[0..NP), least significant first.
+template <int NP>
+__device__ __forceinline__ void crt(const uint32_t (&r)[NP], uint32_t (&z)[NP])
 {
-    uint32_t v[kNumPrimes];
+    uint32_t v[NP];
 #pragma unroll
-    for (int i = 0; i < kNumPrimes; ++i) {
+    for (int i = 0; i < NP; ++i) {
         const uint32_t p = kPrimes[i];
         uint32_t t = r[i];
 #pragma unroll
@@ -95,10 +96,10 @@ __device__ __forceinline__ void crt(const uint32_t (&r)[kNumPrimes], uint32_t (&
         }
         v[i] = t;
     }
-    z[0] = v[kNumPrimes - 1];
+    z[0] = v[NP - 1];
 #pragma unroll
-    for (int i = kNumPrimes - 2; i >= 0; --i) {
-        const int words = kNumPrimes - 1 - i;     // words of the accumulator so far
+    for (int i = NP - 2; i >= 0; --i) {
+        const int words = NP - 1 - i;             // words of the accumulator so far
         uint64_t carry = v[i];
 #pragma unroll
         for (int w = 0; w < words; ++w) {
@@ -139,28 +140,32 @@ __device__ __forceinline__ void bind_job(CarryArgs& a, uint32_t job)
     a.chunks = j.chunks;
 }
 
-// Residues of coefficient K (0 outside [0, ceil(D / 2))).
-__device__ __forceinline__ void load_res(const CarryArgs& a, int64_t K, uint32_t (&r)[kNumPrimes])
+// Residues of coefficient K (0 outside [0, ceil(D / W))).
+template <int W>
+__device__ __forceinline__ void load_res(const CarryArgs& a, int64_t K, uint32_t (&r)[2 * W + 1])
 {
-    const int64_t coeffs = (a.num_digits + 1) >> 1;
+    const int64_t coeffs = (a.num_digits + W - 1) / W;
 #pragma unroll
-    for (int pi = 0; pi < kNumPrimes; ++pi)
+    for (int pi = 0; pi < 2 * W + 1; ++pi)
         r[pi] = (K < 0 || K >= coeffs) ? 0u : a.res[(size_t)pi * a.L + K];
 }
 
 // Exact coefficient K (0 outside the product's coefficients).
-__device__ __forceinline__ void load_coeff(const CarryArgs& a, int64_t K, uint32_t (&z)[kNumPrimes])
+template <int W>
+__device__ __forceinline__ void load_coeff(const CarryArgs& a, int64_t K, uint32_t (&z)[2 * W + 1])
 {
-    uint32_t r[kNumPrimes];
-    load_res(a, K, r);
-    crt(r, z);
+    uint32_t r[2 * W + 1];
+    load_res<W>(a, K, r);
+    crt<2 * W + 1>(r, z);
 }
 
 // kApply = false: write the chunk's carry function.  kApply = true: resolve the
 // chunk with its carry-in and write its output words.
-template <int kPer, bool kApply>
+template <int kPer, bool kApply, int W>
 __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
 {
+    constexpr int NP = 2 * W + 1;              // primes, and words per coefficient
+    static_assert(kPer % W == 0, "a thread owns whole coefficients");
     if (a.jobs) {
         bind_job(a, blockIdx.y);
         if (blockIdx.x >= a.chunks)
@@ -183,20 +188,21 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
 
     // column sums of this thread's kPer digits (and, for the last thread, the
     // two digits past the chunk, which it resolves with the chunk's carry-out);
-    // its digits 2K, 2K + 1 come from coefficients K, K - 1 and K - 2
+    // its digits W K + r come from coefficients K, K - 1 and K - 2
     constexpr int kExtra = 2;
-    constexpr int kCo = kPer / 2;              // coefficients per thread
+    constexpr int kCo = kPer / W;              // coefficients per thread
     uint64_t s[kPer + kExtra];
     const int first = tid * kPer;
     const int count = kPer + (tid == kCarryThreads - 1 ? kExtra : 0);
-    const int64_t kf = k0 + first;             // even
-    const int64_t K0 = kf >> 1;
-    const int64_t coeffs = (D + 1) >> 1;
+    const int64_t kf = k0 + first;             // a multiple of W
+    const int64_t K0 = kf / W;
+    const int64_t coeffs = (D + W - 1) / W;
     // this thread's residues, vector loads when its coefficients lie inside
-    uint32_t r[kNumPrimes][kCo];
+    // (K0 is a multiple of kCo, so they are aligned)
+    uint32_t r[NP][kCo];
     if (K0 + kCo <= coeffs) {
 #pragma unroll
-        for (int pi = 0; pi < kNumPrimes; ++pi) {
+        for (int pi = 0; pi < NP; ++pi) {
             const uint32_t* src = a.res + (size_t)pi * a.L + K0;
             if constexpr (kCo == 2) {
                 const uint2 q = *reinterpret_cast<const uint2*>(src);
@@ -216,10 +222,10 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     } else {
 #pragma unroll
         for (int i = 0; i < kCo; ++i) {
-            uint32_t q[kNumPrimes];
-            load_res(a, K0 + i, q);
+            uint32_t q[NP];
+            load_res<W>(a, K0 + i, q);
 #pragma unroll
-            for (int pi = 0; pi < kNumPrimes; ++pi) r[pi][i] = q[pi];
+            for (int pi = 0; pi < NP; ++pi) r[pi][i] = q[pi];
         }
     }
     // Exact coefficients of this thread.  The high words of the two before its
@@ -227,58 +233,66 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     // the chunk's boundary coefficients, and the last thread's two extra digits
     // need the coefficient past the chunk: lane 0 of waves 1, 2 and 3 computes
     // one each, so that no wave runs more than one CRT beyond its own.
-    uint32_t z[kCo][kNumPrimes];
+    uint32_t z[kCo][NP];
 #pragma unroll
     for (int ci = 0; ci < kCo; ++ci) {
-        uint32_t q[kNumPrimes];
+        uint32_t q[NP];
 #pragma unroll
-        for (int pi = 0; pi < kNumPrimes; ++pi) q[pi] = r[pi][ci];
-        crt(q, z[ci]);
+        for (int pi = 0; pi < NP; ++pi) q[pi] = r[pi][ci];
+        crt<NP>(q, z[ci]);
     }
-    // hw[t + 1] = words 2, 3, 4 of thread t's last coefficient and word 4 of
-    // the one before it; hw[0] the same for the two coefficients before the chunk
-    __shared__ uint4 hw[kCarryThreads + 1];
+    // hw[t + 1] = words W .. 2 W of thread t's last coefficient, then word 2 W
+    // of the one before it; hw[0] the same for the two coefficients before the
+    // chunk
+    constexpr int kHw = W + 2;
+    __shared__ uint32_t hw[kCarryThreads + 1][kHw];
     __shared__ uint32_t tail[2];
     static_assert(kCarryThreads == 256, "boundary coefficients go to waves 1, 2 and 3");
-    hw[tid + 1] = make_uint4(z[kCo - 1][2], z[kCo - 1][3], z[kCo - 1][4], z[kCo - 2][4]);
+#pragma unroll
+    for (int w = 0; w <= W; ++w) hw[tid + 1][w] = z[kCo - 1][W + w];
+    hw[tid + 1][W + 1] = z[kCo - 2][2 * W];
     {
-        const int64_t Kc = k0 >> 1;            // first coefficient of the chunk
-        uint32_t q[kNumPrimes];
+        const int64_t Kc = k0 / W;             // first coefficient of the chunk
+        uint32_t q[NP];
         if (tid == 64) {
-            load_coeff(a, Kc - 1, q);
-            hw[0].x = q[2];
-            hw[0].y = q[3];
-            hw[0].z = q[4];
+            load_coeff<W>(a, Kc - 1, q);
+#pragma unroll
+            for (int w = 0; w <= W; ++w) hw[0][w] = q[W + w];
         } else if (tid == 128) {
-            load_coeff(a, Kc - 2, q);
-            hw[0].w = q[4];
+            load_coeff<W>(a, Kc - 2, q);
+            hw[0][W + 1] = q[2 * W];
         } else if (tid == 192) {
-            load_coeff(a, Kc + kChunk / 2, q);
+            load_coeff<W>(a, Kc + kChunk / W, q);
             tail[0] = q[0];
             tail[1] = q[1];
         }
     }
     __syncthreads();
     {
-        const uint4 h = hw[tid];
-        uint32_t prev_w2 = h.x, prev_w3 = h.y, prev_w4 = h.z, prev2_w4 = h.w;
+        // prev[w] = word W + w of the previous coefficient (w <= W), prev2 =
+        // word 2 W of the one before it
+        uint32_t prev[W + 1];
 #pragma unroll
-        for (int ci = 0; ci < kCo + kExtra / 2; ++ci) {
-            if (2 * ci < count) {
-                const bool own = ci < kCo;
-                const uint32_t w0 = own ? z[ci % kCo][0] : tail[0];
-                const uint32_t w1 = own ? z[ci % kCo][1] : tail[1];
-                const int64_t k = kf + 2 * ci;
-                const uint32_t d0 = (k < (int64_t)D) ? addend_digit(a, (uint32_t)k) : 0u;
-                const uint32_t d1 = (k + 1 < (int64_t)D) ? addend_digit(a, (uint32_t)(k + 1)) : 0u;
-                s[2 * ci] = (k < (int64_t)D) ? (uint64_t)w0 + prev_w2 + prev2_w4 + d0 : 0ull;
-                s[2 * ci + 1] = (k + 1 < (int64_t)D) ? (uint64_t)w1 + prev_w3 + d1 : 0ull;
-                if (own) {
-                    prev2_w4 = prev_w4;
-                    prev_w2 = z[ci % kCo][2];
-                    prev_w3 = z[ci % kCo][3];
-                    prev_w4 = z[ci % kCo][4];
+        for (int w = 0; w <= W; ++w) prev[w] = hw[tid][w];
+        uint32_t prev2 = hw[tid][W + 1];
+#pragma unroll
+        for (int ci = 0; ci < kCo + 1; ++ci) {
+            const bool own = ci < kCo;
+#pragma unroll
+            for (int rr = 0; rr < W; ++rr) {
+                const int i = W * ci + rr;
+                if (i < count && i < kPer + kExtra) {
+                    const uint32_t zw = own ? z[ci % kCo][rr] : (rr < 2 ? tail[rr % 2] : 0u);
+                    const int64_t k = kf + i;
+                    const uint32_t d = (k < (int64_t)D) ? addend_digit(a, (uint32_t)k) : 0u;
+                    s[i % (kPer + kExtra)] = (k < (int64_t)D)
+                        ? (uint64_t)zw + prev[rr] + (rr == 0 ? prev2 : 0u) + d : 0ull;
                 }
+            }
+            if (own) {
+                prev2 = prev[W];
+#pragma unroll
+                for (int w = 0; w <= W; ++w) prev[w] = z[ci % kCo][W + w];
             }
         }
     }
@@ -372,8 +386,10 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
 #define PA_CARRY_PER_LARGE 8
 #endif
 
-int carry_digits_per_thread(uint32_t num_digits)
+int carry_digits_per_thread(uint32_t num_digits, int W)
 {
+    if (W == 3)
+        return num_digits >= (1u << 20) ? 12 : 6;
     return num_digits >= (1u << 18) ? PA_CARRY_PER_LARGE : 4;
 }
 
@@ -391,10 +407,17 @@ template <bool kApply>
 void launch_chunks(const CarryArgs& a, hipStream_t stream, unsigned batch, const LaunchEvents& ev)
 {
     const dim3 grid(a.chunks, batch);
+    if (a.dwords == 3) {
+        if (a.per == 12)
+            launch_timed(k_carry<12, kApply, 3>, grid, dim3(kCarryThreads), stream, ev, a);
+        else
+            launch_timed(k_carry<6, kApply, 3>, grid, dim3(kCarryThreads), stream, ev, a);
+        return;
+    }
     switch (a.per) {
-    case 16: launch_timed(k_carry<16, kApply>, grid, dim3(kCarryThreads), stream, ev, a); break;
-    case 8: launch_timed(k_carry<8, kApply>, grid, dim3(kCarryThreads), stream, ev, a); break;
-    default: launch_timed(k_carry<4, kApply>, grid, dim3(kCarryThreads), stream, ev, a); break;
+    case 16: launch_timed(k_carry<16, kApply, 2>, grid, dim3(kCarryThreads), stream, ev, a); break;
+    case 8: launch_timed(k_carry<8, kApply, 2>, grid, dim3(kCarryThreads), stream, ev, a); break;
+    default: launch_timed(k_carry<4, kApply, 2>, grid, dim3(kCarryThreads), stream, ev, a); break;
     }
 }
 

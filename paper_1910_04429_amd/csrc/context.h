@@ -11,11 +11,11 @@ struct pa_ctx {
     // tables
     uint32_t* pass_lo = nullptr;
     uint32_t* pass_hi = nullptr;
-    // workspace, sized for cap_L / cap_D
+    // workspace: cap_L residues per array (all primes), carry state for cap_D digits
     uint64_t cap_L = 0, cap_D = 0;
-    uint32_t* A = nullptr;            // c-hat   [3][L]
-    uint32_t* B = nullptr;            // x-hat, then the product residues [3][L]
-    uint32_t* status = nullptr;       // carry state: [chunks] functions, [chunks] carries
+    uint32_t* A = nullptr;            // c-hat   [primes][L]
+    uint32_t* B = nullptr;            // x-hat, then the product residues [primes][L]
+    uint32_t* status = nullptr;       // carry state: the carry function of each chunk
     // staging for the synchronous (host memory) entry points
     uint64_t cap_words = 0;
     uint64_t* d_key = nullptr;
@@ -27,7 +27,7 @@ struct pa_ctx {
     uint64_t* tbits = nullptr;
     // chosen plan geometry per transform length (slot: k, or 32 + k for 3 2^k);
     // t == 0: the defaults
-    static constexpr int kPlanSlots = 64;
+    static constexpr int kPlanSlots = 128;   // (W == 3) 64 + (f == 3) 32 + k
     struct PlanChoice {
         int t = 0, ts = 0, r0 = 0;
     } plans[kPlanSlots];

@@ -2,11 +2,11 @@
 //
 // The hash needs the low n bits of c*x (Section 2.3, the g_{c,d} definition;
 // Section 3.2.2, the large multiply done by an NTT convolution as in Alg. 1).
-// Operands are cut into 64-bit digits (the key's own words); the convolution
-// coefficients sum_{i+j=k} x_i c_j are below D (2^64-1)^2 < 2^151 for D <= 2^23
-// digits and are recovered exactly by CRT from five NTTs over 31-bit primes
-// whose product is about 2^153.4.  Every prime is k 3 2^25 + 1, so every
-// length 2^k and 3 2^k up to 3 2^25 has a root of unity in each field.
+// Operands are cut into digits of W = 2 or 3 32-bit words (64 or 96 bits); the
+// convolution coefficients sum_{i+j=k} x_i c_j are below D 2^{64 W} and are
+// recovered exactly by CRT from 2 W + 1 NTTs over 31-bit primes: five primes
+// (product 2^153.4 > 2^23 2^128) for 64-bit digits, seven (product 2^215.2 >
+// 2^22.5 2^192) for 96-bit digits, at every n up to 2^29 bits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,12 +14,16 @@
 
 namespace pa {
 
-constexpr int kNumPrimes = 5;
-constexpr int kLogMaxLen = 25;                 // min 2-adicity of the primes
-// Every transform length divides kOrder = 3 * 2^25, which divides p - 1 for
-// each prime (quotients 20, 18, 21, 17 and 11): one root of unity of order
-// kOrder per prime generates the twiddles of every length 2^k and 3 * 2^k.
-// These five are all the primes of the form k 3 2^25 + 1 below 2^31.
+constexpr int kNumPrimes = 7;
+constexpr int kLogMaxLen = 25;                 // min 2-adicity of the first five primes
+// Twiddle exponents are counted in units of one root of order kOrder =
+// 3 * 2^25.  The first five primes are all the primes k 3 2^25 + 1 below 2^31
+// (quotients 20, 18, 21, 17 and 11), so they have such a root and serve every
+// length 2^k and 3 * 2^k up to kOrder.  The last two only have roots of order
+// kOrder / 8 = 3 * 2^22: their root r stands for w^8, exponent E of w is power
+// E / 8 of r, which is exact for every length up to 3 * 2^22 (all exponents
+// used are then multiples of 8).  They serve the 96-bit-digit layout only,
+// whose transforms stay within that length.
 constexpr uint32_t kOrder = 3u << kLogMaxLen;
 constexpr uint32_t kPrimes[kNumPrimes] = {
     2013265921u,  // 15 * 2^27 + 1
@@ -27,7 +31,14 @@ constexpr uint32_t kPrimes[kNumPrimes] = {
     2113929217u,  // 63 * 2^25 + 1
     1711276033u,  // 51 * 2^25 + 1
     1107296257u,  // 33 * 2^25 + 1
+    2088763393u,  // 249 * 2^23 + 1
+    2025848833u,  // 483 * 2^22 + 1
 };
+// log2 of kOrder / (order of the prime's root): 0 or 3.
+constexpr int kRootShift[kNumPrimes] = {0, 0, 0, 0, 0, 3, 3};
+// Longest transform of each layout (W = 2: five primes; W = 3: seven).
+constexpr uint32_t kMaxLen64 = kOrder;
+constexpr uint32_t kMaxLen96 = kOrder >> 3;
 
 // -p^{-1} mod 2^32 by Newton iteration (each step doubles the correct bits).
 constexpr uint32_t neg_inverse_u32(uint32_t p)
@@ -40,7 +51,8 @@ constexpr uint32_t neg_inverse_u32(uint32_t p)
 
 constexpr uint32_t kNegInv[kNumPrimes] = {
     neg_inverse_u32(kPrimes[0]), neg_inverse_u32(kPrimes[1]), neg_inverse_u32(kPrimes[2]),
-    neg_inverse_u32(kPrimes[3]), neg_inverse_u32(kPrimes[4])};
+    neg_inverse_u32(kPrimes[3]), neg_inverse_u32(kPrimes[4]), neg_inverse_u32(kPrimes[5]),
+    neg_inverse_u32(kPrimes[6])};
 
 constexpr uint64_t pow_mod(uint64_t b, uint64_t e, uint64_t p)
 {
@@ -83,21 +95,23 @@ constexpr uint32_t primitive_root(uint64_t p)
 }
 
 // The root of unity of order kOrder that every twiddle is a power of.
-constexpr uint32_t order_root(uint64_t p)
+constexpr uint32_t order_root(uint64_t p, int shift)
 {
-    return (uint32_t)pow_mod(primitive_root(p), (p - 1) / kOrder, p);
+    return (uint32_t)pow_mod(primitive_root(p), (p - 1) / (kOrder >> shift), p);
 }
 
-constexpr uint32_t kRoot[kNumPrimes] = {order_root(kPrimes[0]), order_root(kPrimes[1]),
-                                        order_root(kPrimes[2]), order_root(kPrimes[3]),
-                                        order_root(kPrimes[4])};
+constexpr uint32_t kRoot[kNumPrimes] = {
+    order_root(kPrimes[0], kRootShift[0]), order_root(kPrimes[1], kRootShift[1]),
+    order_root(kPrimes[2], kRootShift[2]), order_root(kPrimes[3], kRootShift[3]),
+    order_root(kPrimes[4], kRootShift[4]), order_root(kPrimes[5], kRootShift[5]),
+    order_root(kPrimes[6], kRootShift[6])};
 
 // Shoup quotient floor(w 2^32 / p) of a constant w < p.
 constexpr uint32_t shoup_quotient(uint64_t w, uint64_t p) { return (uint32_t)((w << 32) / p); }
 
-// Garner's mixed-radix CRT: with v_0 = r_0 and
+// Garner's mixed-radix CRT over the first P primes: with v_0 = r_0 and
 //   v_i = (...((r_i - v_0) p_0^{-1} - v_1) p_1^{-1} ... - v_{i-1}) p_{i-1}^{-1}  mod p_i,
-// the coefficient is v_0 + p_0 (v_1 + p_1 (v_2 + p_2 (v_3 + p_3 v_4))).
+// the coefficient is v_0 + p_0 (v_1 + p_1 (v_2 + ... + p_{P-2} v_{P-1})).
 // kGarner[i][j] is p_j^{-1} mod p_i in Montgomery form (j < i).
 struct GarnerTable {
     uint32_t inv[kNumPrimes][kNumPrimes];
@@ -118,18 +132,20 @@ constexpr bool primes_ok()
         const uint64_t p = kPrimes[i];
         // odd, 2^30 < p < 2^31: a residue of any of the primes is below 2 p
         if (p % 2 == 0 || p <= (1ull << 30) || p >= (1ull << 31)) return false;
-        if ((p - 1) % kOrder != 0) return false;
+        const uint64_t order = kOrder >> kRootShift[i];
+        if ((p - 1) % order != 0) return false;
         if ((uint32_t)(kNegInv[i] * (uint32_t)p) != 0xFFFFFFFFu) return false;
-        // the root has order exactly 3 * 2^25
-        if (pow_mod(kRoot[i], kOrder, p) != 1 || pow_mod(kRoot[i], kOrder / 2, p) == 1 ||
-            pow_mod(kRoot[i], kOrder / 3, p) == 1)
+        // the root has order exactly 3 * 2^25 (or 3 * 2^22)
+        if (pow_mod(kRoot[i], order, p) != 1 || pow_mod(kRoot[i], order / 2, p) == 1 ||
+            pow_mod(kRoot[i], order / 3, p) == 1)
             return false;
         for (int j = 0; j < i; ++j)
             if (kPrimes[j] == p) return false;
     }
     return true;
 }
-static_assert(primes_ok(), "five distinct primes in (2^30, 2^31) with roots of order 3 * 2^25");
+static_assert(primes_ok(), "seven distinct primes in (2^30, 2^31) with roots of order 3 * 2^25 "
+                           "(the first five) or 3 * 2^22");
 
 // ---------------------------------------------------------------------------
 // Canonical residues in [0, p), p < 2^31.

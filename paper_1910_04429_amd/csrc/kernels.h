@@ -27,7 +27,7 @@ struct Tables {
 
 enum Source : int {
     kSrcArray = 0,   // residues already in `data`
-    kSrcDigits = 1,  // 64-bit digits (the words) of an n-bit operand in memory
+    kSrcDigits = 1,  // digits of W 32-bit words of an n-bit operand in memory
     kSrcSeed = 2,    // words of the SplitMix64 stream of `seed`, bit 0 forced to 1
     kSrcBits = 3,    // element e = bit bit_off + e of `digits` for e < n, else 0
 };
@@ -43,9 +43,9 @@ struct JobDesc {
     uint64_t n, m;
     uint32_t num_digits;       // ceil(n / 32)
     uint32_t chunks;           // carry chunks
-    uint32_t* A;               // c-hat [kNumPrimes][L]
-    uint32_t* B;               // x-hat, then the product [kNumPrimes][L]
-    uint32_t* carry;           // [2 * chunks]: chunk functions, then carries in
+    uint32_t* A;               // c-hat [primes][L]
+    uint32_t* B;               // x-hat, then the product [primes][L]
+    uint32_t* carry;           // carry state: the carry function of each chunk
     uint64_t* out;             // ceil(m / 64) words
 };
 
@@ -68,7 +68,7 @@ enum PassMode : int {
 // tile the length-R transform runs as register steps: a radix-3 step first when
 // f = 3, then nsteps steps of radix 2^steps[i].
 struct PassArgs {
-    uint32_t* data;            // [kNumPrimes][L]
+    uint32_t* data;            // [primes][L]
     const uint32_t* other;     // kFused: pre-scaled c-hat, same layout
     const uint32_t* digits;    // kSrcDigits: the operand's words as ceil(n/32) 32-bit halves
     uint64_t seed;             // kSrcSeed
@@ -88,7 +88,8 @@ struct PassArgs {
     int scale;                 // multiply the stored output by scale_w (Shoup)
     uint32_t scale_w[kNumPrimes], scale_q[kNumPrimes];
     Tables tb;
-    int primes;                // primes transformed (grid.y); 0 means all kNumPrimes
+    int primes;                // primes transformed (grid.y): 2 W + 1, or 1 (Toeplitz)
+    int dwords;                // W: 32-bit words per digit of a kSrcDigits/kSrcSeed source
     // dual launch (single block, grid.z = 2, seeded multiplier): workgroups with
     // blockIdx.z == 1 run the key's first pass, of the same geometry, with the
     // key digits in `digits` and its spectrum in `other` (both unused by the
@@ -98,15 +99,16 @@ struct PassArgs {
     const JobDesc* jobs;
     int role;
     int limit_to_digits;       // store only the product's coefficients: positions
-                               // below ceil(ceil(D / 2) / 4) * 4
+                               // below ceil(ceil(D / W) / 4) * 4
 };
 
 // CRT, carry propagation, addend and bit extraction over the product.
 constexpr int kCarryThreads = 256;
 
 struct CarryArgs {
-    const uint32_t* res;       // [kNumPrimes][L] residues of the product (natural order)
+    const uint32_t* res;       // [2 W + 1][L] residues of the product (natural order)
     uint32_t L;
+    int dwords;                // W: a coefficient sits at 32-bit positions W K .. W K + 2 W
     uint32_t num_digits;       // D = ceil(n / 32)
     uint64_t n, m;
     int addend_src;            // kSrcDigits or kSrcSeed (no forced odd bit)
@@ -115,7 +117,7 @@ struct CarryArgs {
     uint32_t* desc;            // [chunks] carry function of each chunk
     uint64_t* out;             // ceil(m / 64) words
     uint32_t chunks;           // grid width (the largest chunk count in a batch)
-    int per;                   // digits per thread (4, 8 or 16)
+    int per;                   // digits per thread (W = 2: 4 or 8; W = 3: 6 or 12)
     const JobDesc* jobs;       // batch mode: per-block fields from jobs[blockIdx.y]
 };
 
@@ -125,8 +127,9 @@ struct LaunchEvents {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
-// Digits per thread of the carry kernel for a block of D digits.
-int carry_digits_per_thread(uint32_t num_digits);
+// 32-bit digits per thread of the carry kernel for a block of D of them, with
+// coefficients of W words (a multiple of W).
+int carry_digits_per_thread(uint32_t num_digits, int W);
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch = 1,
                        const LaunchEvents& ev = {});

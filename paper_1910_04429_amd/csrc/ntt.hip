@@ -1,8 +1,9 @@
-// Multi-pass number-theoretic transform over the five primes of field.h.
+// Multi-pass number-theoretic transform over the primes of field.h (five for
+// 64-bit digits, seven for 96-bit digits).
 //
-// The product c*x is a cyclic convolution of the two vectors of 64-bit digits
-// padded to a length L >= 2D - 1 (Alg. 1: fill zero, split, evaluate,
-// pointwise multiply, interpolate).  A length-L transform is a short sequence of passes; each pass
+// The product c*x is a cyclic convolution of the two digit vectors padded to a
+// length L >= 2D - 1 (Alg. 1: fill zero, split, evaluate, pointwise multiply,
+// interpolate).  A length-L transform is a short sequence of passes; each pass
 // works on LDS tiles of at most 2^14 residues of one prime (64 KB) and reads
 // and writes its array once.
 //
@@ -63,14 +64,17 @@ template <int PI>
 struct PrimeConst {
     static constexpr uint32_t p = kPrimes[PI];
     static constexpr uint32_t pneg = kNegInv[PI];
-    static constexpr uint64_t w64 = pow_mod(kRoot[PI], kOrder / 64, kPrimes[PI]);
+    static constexpr uint64_t order = kOrder >> kRootShift[PI];   // of the prime's root
+    static constexpr uint64_t w64 = pow_mod(kRoot[PI], order / 64, kPrimes[PI]);
     static constexpr uint64_t w64inv = pow_mod(w64, kPrimes[PI] - 2, kPrimes[PI]);
-    static constexpr uint64_t w3 = pow_mod(kRoot[PI], kOrder / 3, kPrimes[PI]);
+    static constexpr uint64_t w3 = pow_mod(kRoot[PI], order / 3, kPrimes[PI]);
     static constexpr uint64_t w3sq = w3 * w3 % kPrimes[PI];
-    // 2^32 mod p and its Shoup quotient: a 64-bit digit hi 2^32 + lo is
-    // hi (2^32 mod p) + lo mod p
+    // 2^32 and 2^64 mod p with their Shoup quotients: a digit of words
+    // (w0, w1, w2) is w0 + w1 (2^32 mod p) + w2 (2^64 mod p) mod p
     static constexpr uint32_t r32 = (uint32_t)((1ull << 32) % kPrimes[PI]);
     static constexpr uint32_t r32q = shoup_quotient(r32, kPrimes[PI]);
+    static constexpr uint32_t r64 = (uint32_t)((uint64_t)r32 * r32 % kPrimes[PI]);
+    static constexpr uint32_t r64q = shoup_quotient(r64, kPrimes[PI]);
 };
 
 // A 64-bit digit (lo, hi) reduced mod prime PI.
@@ -79,6 +83,14 @@ __device__ __forceinline__ uint32_t reduce64(uint32_t lo, uint32_t hi)
 {
     constexpr uint32_t p = PrimeConst<PI>::p;
     return fadd(freduce32(lo, p), fmul_shoup(hi, PrimeConst<PI>::r32, PrimeConst<PI>::r32q, p), p);
+}
+
+// A 96-bit digit (w0, w1, w2) reduced mod prime PI.
+template <int PI>
+__device__ __forceinline__ uint32_t reduce96(uint32_t w0, uint32_t w1, uint32_t w2)
+{
+    constexpr uint32_t p = PrimeConst<PI>::p;
+    return fadd(reduce64<PI>(w0, w1), fmul_shoup(w2, PrimeConst<PI>::r64, PrimeConst<PI>::r64q, p), p);
 }
 
 // omega_64^e (kInv: omega_64^{-e}) and its Shoup quotient, e < 32.
@@ -138,7 +150,7 @@ __device__ __forceinline__ BlockView block_view(const PassArgs& a)
             }
         }
         if (a.limit_to_digits)
-            v.store_limit = (((j.num_digits + 1u) >> 1) + 3u) & ~3u;
+            v.store_limit = ((j.num_digits + a.dwords - 1u) / a.dwords + 3u) & ~3u;
     } else if (a.dual && blockIdx.z == 1) {
         v.data = const_cast<uint32_t*>(a.other);
         v.src = kSrcDigits;
@@ -146,45 +158,48 @@ __device__ __forceinline__ BlockView block_view(const PassArgs& a)
     return v;
 }
 
-// 64-bit digits pos .. pos + 3 (pos a multiple of 4) of the operand described
-// by the block's source as eight 32-bit halves, low half first, 0 beyond bit
-// n: two 16-byte loads of key words, or four SplitMix64 words of a seeded
-// multiplier (bit 0 forced to 1, eq. (6)).
-__device__ __forceinline__ void source_quad(const BlockView& a, uint32_t pos, uint32_t (&v)[8])
+// Digits pos .. pos + 3 (pos a multiple of 4) of W 32-bit words each of the
+// operand described by the block's source, as 4 W words, low word first, 0
+// beyond bit n: W 16-byte loads of key words, or 2 W SplitMix64 words of a
+// seeded multiplier (bit 0 forced to 1, eq. (6)).
+template <int W>
+__device__ __forceinline__ void source_quad(const BlockView& a, uint32_t pos, uint32_t (&v)[4 * W])
 {
-    const uint32_t D = a.num_digits;          // 32-bit digits of the operand
-    const uint32_t d0 = 2 * pos;
+    const uint32_t D = a.num_digits;          // 32-bit words of the operand
+    const uint32_t d0 = W * pos;              // even: pos is a multiple of 4
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = 0u;
+    for (int i = 0; i < 4 * W; ++i) v[i] = 0u;
     if (d0 >= D)
         return;
     if (a.src == kSrcDigits) {
-        if (d0 + 8 <= D && (reinterpret_cast<uintptr_t>(a.digits) & 15u) == 0) {
-            const uint4 q0 = *reinterpret_cast<const uint4*>(a.digits + d0);
-            const uint4 q1 = *reinterpret_cast<const uint4*>(a.digits + d0 + 4);
-            v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w;
-            v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
+        if (d0 + 4 * W <= D && (reinterpret_cast<uintptr_t>(a.digits) & 15u) == 0) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const uint4 t = *reinterpret_cast<const uint4*>(a.digits + d0 + 4 * q);
+                v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+            }
         } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int i = 0; i < 4 * W; ++i)
                 if (d0 + i < D) v[i] = a.digits[d0 + i];
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < 2 * W; ++e) {
             if (d0 + 2 * e < D) {
-                const uint64_t w = splitmix64(a.seed, pos + e);
-                v[2 * e] = (uint32_t)w | ((pos + e == 0) ? 1u : 0u);
+                const uint32_t idx = (d0 >> 1) + e;
+                const uint64_t w = splitmix64(a.seed, idx);
+                v[2 * e] = (uint32_t)w | ((idx == 0) ? 1u : 0u);
                 v[2 * e + 1] = (d0 + 2 * e + 1 < D) ? (uint32_t)(w >> 32) : 0u;
             }
         }
     }
-    // bits past n in the top 32-bit digit
+    // bits past n in the top 32-bit word
     const uint32_t top = (uint32_t)(a.n & 31);
     if (top) {
         const uint32_t mask = (1u << top) - 1u;
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 4 * W; ++i)
             if (d0 + i == D - 1) v[i] &= mask;
     }
 }
@@ -198,7 +213,8 @@ __device__ __forceinline__ uint32_t source_bit(const BlockView& a, uint32_t t)
     return (a.digits[b >> 5] >> (b & 31)) & 1u;
 }
 
-// Montgomery form of w^E for the root w of order kOrder, E < kOrder.
+// Montgomery form of w^E for the root w of order kOrder, E < kOrder (for a
+// prime whose root has order kOrder / 8: r^(E / 8), E a multiple of 8).
 template <int PI>
 __device__ __forceinline__ uint32_t root_pow(const Tables& tb, uint32_t E)
 {
@@ -588,8 +604,9 @@ __device__ __forceinline__ void dispatch_fused_middle(int r, uint32_t* sm, int N
     }
 }
 
-// One pass over the tile of prime PI owned by this workgroup.
-template <int PI>
+// One pass over the tile of prime PI owned by this workgroup; digit sources
+// have W 32-bit words per digit.
+template <int PI, int W>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
 {
     constexpr uint32_t p = PrimeConst<PI>::p;
@@ -646,9 +663,16 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
             v.y = source_bit(bv, pos + 1);
             v.z = source_bit(bv, pos + 2);
             v.w = source_bit(bv, pos + 3);
+        } else if constexpr (W == 3) {
+            uint32_t h[12];
+            source_quad<3>(bv, pos, h);
+            v.x = reduce96<PI>(h[0], h[1], h[2]);
+            v.y = reduce96<PI>(h[3], h[4], h[5]);
+            v.z = reduce96<PI>(h[6], h[7], h[8]);
+            v.w = reduce96<PI>(h[9], h[10], h[11]);
         } else {
             uint32_t h[8];
-            source_quad(bv, pos, h);
+            source_quad<2>(bv, pos, h);
             v.x = reduce64<PI>(h[0], h[1]);
             v.y = reduce64<PI>(h[2], h[3]);
             v.z = reduce64<PI>(h[4], h[5]);
@@ -726,15 +750,31 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
     }
 }
 
+// One kernel per layout: W = 2 (64-bit digits, the first five primes; also the
+// Toeplitz variant's bit sources over prime 0) and W = 3 (96-bit digits, all
+// seven), so that neither carries the other's primes and sources.
+template <int W>
 __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
 {
     extern __shared__ uint32_t sm[];          // 4 N bytes
-    switch (blockIdx.y) {
-    case 0: pass_tile<0>(a, sm); break;
-    case 1: pass_tile<1>(a, sm); break;
-    case 2: pass_tile<2>(a, sm); break;
-    case 3: pass_tile<3>(a, sm); break;
-    default: pass_tile<4>(a, sm); break;
+    if constexpr (W == 3) {
+        switch (blockIdx.y) {
+        case 0: pass_tile<0, W>(a, sm); break;
+        case 1: pass_tile<1, W>(a, sm); break;
+        case 2: pass_tile<2, W>(a, sm); break;
+        case 3: pass_tile<3, W>(a, sm); break;
+        case 4: pass_tile<4, W>(a, sm); break;
+        case 5: pass_tile<5, W>(a, sm); break;
+        default: pass_tile<6, W>(a, sm); break;
+        }
+    } else {
+        switch (blockIdx.y) {
+        case 0: pass_tile<0, W>(a, sm); break;
+        case 1: pass_tile<1, W>(a, sm); break;
+        case 2: pass_tile<2, W>(a, sm); break;
+        case 3: pass_tile<3, W>(a, sm); break;
+        default: pass_tile<4, W>(a, sm); break;
+        }
     }
 }
 
@@ -748,12 +788,15 @@ hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch, co
     const uint32_t first = a.f == 3 ? 3u : (1u << (a.steps_code & 15u));
     uint32_t threads = N / first;
     threads = threads < 64 ? 64 : (threads > kPassThreads ? kPassThreads : threads);
-    const unsigned primes = a.primes > 0 && a.primes < kNumPrimes ? (unsigned)a.primes : kNumPrimes;
+    const bool w3 = a.dwords == 3;
+    if (a.primes < 1 || a.primes > (w3 ? 7 : 5)) return hipErrorInvalidValue;
+    const unsigned primes = (unsigned)a.primes;
+    auto kernel = w3 ? k_pass<3> : k_pass<2>;
     if (ev.start)
-        hipExtLaunchKernelGGL(k_pass, dim3(tiles, primes, batch), dim3(threads),
+        hipExtLaunchKernelGGL(kernel, dim3(tiles, primes, batch), dim3(threads),
                               sizeof(uint32_t) * N, stream, ev.start, ev.stop, 0, a);
     else
-        hipLaunchKernelGGL(k_pass, dim3(tiles, primes, batch), dim3(threads),
+        hipLaunchKernelGGL(kernel, dim3(tiles, primes, batch), dim3(threads),
                            sizeof(uint32_t) * N, stream, a);
     return hipGetLastError();
 }

@@ -50,12 +50,13 @@ int fail(pa_ctx* ctx, int code, const char* what, hipError_t e = hipSuccess)
 
 uint64_t words_of(uint64_t bits) { return (bits + 63) / 64; }
 uint64_t digits_of(uint64_t bits) { return (bits + 31) / 32; }
-// Transform elements of an n-bit operand: its 64-bit digits.
-uint64_t coeffs_of(uint64_t bits) { return (bits + 63) / 64; }
+// Transform elements of an n-bit operand cut into digits of W 32-bit words.
+uint64_t coeffs_of(uint64_t bits, int W) { return (bits + 32ull * W - 1) / (32ull * W); }
 
-// Transform length for a block of n bits cut into D = ceil(n / 64) digits:
+// Transform length for a block of n bits cut into D = ceil(n / 32 W) digits:
 // the smallest L >= 2D - 1 among 2^l and, for long transforms, 3 * 2^(l-2) (a
-// quarter shorter when it fits, as for n = 10^8: 2D - 1 = 3 124 999 <= 3 * 2^20).
+// quarter shorter when it fits, as for n = 10^8 with 64-bit digits:
+// 2D - 1 = 3 124 999 <= 3 * 2^20).
 #ifndef PA_MIXED_RADIX_MIN_LOG
 #define PA_MIXED_RADIX_MIN_LOG 18
 #endif
@@ -63,9 +64,11 @@ uint64_t coeffs_of(uint64_t bits) { return (bits + 63) / 64; }
 static_assert(PA_MIXED_RADIX_MIN_LOG >= kTileLog + 4, "factor-3 pass needs a strided head");
 
 struct Len {
-    int f;   // 1 or 3
-    int k;   // L = f 2^k
+    int f;       // 1 or 3
+    int k;       // L = f 2^k
+    int W = 2;   // digit words: 2 (64-bit digits, five primes) or 3 (96-bit, seven)
     uint64_t L() const { return (uint64_t)f << k; }
+    int primes() const { return 2 * W + 1; }
 };
 
 // Smallest transform length >= need (at least 64).
@@ -77,25 +80,54 @@ Len len_for(uint64_t need)
     return {1, l};
 }
 
-Len plan_len(uint64_t n) { return len_for(2 * coeffs_of(n) - 1); }
+// Layout and length for an n-bit block: of 64-bit digits over five primes and
+// 96-bit digits over seven, the one with less transform work, primes x L x
+// log2 L (96-bit digits only up to their longest transform, 3 2^22).  At
+// n = 10^8: 5 x 3 2^20 against 7 x 2^21, the second; at 10^6: 5 x 2^15 against
+// 7 x 2^15, the first.
+Len plan_len(uint64_t n)
+{
+    Len a = len_for(2 * coeffs_of(n, 2) - 1);
+    Len b = len_for(2 * coeffs_of(n, 3) - 1);
+    b.W = 3;
+    if (b.L() > kMaxLen96) return a;
+    auto work = [](const Len& x) {
+        return (double)x.primes() * (double)x.L() * (x.k + (x.f == 3 ? 1.585 : 0.0));
+    };
+    return work(b) < work(a) ? b : a;
+}
 
 uint64_t len_of(uint64_t n) { return plan_len(n).L(); }
+
+// Residues per spectrum array (all primes) of an n-bit block.
+uint64_t arr_elems(uint64_t n)
+{
+    const Len len = plan_len(n);
+    return (uint64_t)len.primes() * len.L();
+}
+
+// Blocks with equal keys share every launch of a batch group.
+uint64_t layout_key(uint64_t n)
+{
+    const Len len = plan_len(n);
+    return (len.L() << 2) | (uint64_t)len.W;
+}
 
 // Coefficients the carry apply kernel reads for an n-bit block with an m-bit
 // output: those of the chunks that hold an output word's first bit (chunks
 // wholly below bit n - m return at once).
-uint64_t window_coeffs(uint64_t n, uint64_t m)
+uint64_t window_coeffs(uint64_t n, uint64_t m, int W)
 {
     const uint64_t D = (n + 31) / 32;
-    const uint64_t chunk = (uint64_t)kCarryThreads * carry_digits_per_thread((uint32_t)D);
-    const uint64_t skipped = ((n - m) / 32 / chunk) * chunk / 2;
-    const uint64_t total = (n + 63) / 64;
+    const uint64_t chunk = (uint64_t)kCarryThreads * carry_digits_per_thread((uint32_t)D, W);
+    const uint64_t skipped = ((n - m) / 32 / chunk) * chunk / W;
+    const uint64_t total = coeffs_of(n, W);
     return skipped < total ? total - skipped : 0;
 }
 
-uint32_t chunks_of(uint64_t D)
+uint32_t chunks_of(uint64_t D, int W)
 {
-    const uint64_t chunk = (uint64_t)kCarryThreads * carry_digits_per_thread((uint32_t)D);
+    const uint64_t chunk = (uint64_t)kCarryThreads * carry_digits_per_thread((uint32_t)D, W);
     return (uint32_t)((D + chunk - 1) / chunk);
 }
 
@@ -173,29 +205,29 @@ void free_workspace(pa_ctx* ctx)
     ctx->cap_L = ctx->cap_D = 0;
 }
 
-// Grow the workspace to arrays of kNumPrimes * L residues and the carry state
-// of D digits, keeping any larger capacity it already has.
-int ensure_caps(pa_ctx* ctx, uint64_t L, uint64_t D)
+// Grow the workspace to two arrays of `elems` residues and the carry state of
+// D digits, keeping any larger capacity it already has.
+int ensure_caps(pa_ctx* ctx, uint64_t elems, uint64_t D)
 {
-    if (L <= ctx->cap_L && D <= ctx->cap_D)
+    if (elems <= ctx->cap_L && D <= ctx->cap_D)
         return PA_OK;
-    L = std::max(L, ctx->cap_L);
+    elems = std::max(elems, ctx->cap_L);
     D = std::max(D, ctx->cap_D);
     PA_HIP(ctx, hipDeviceSynchronize());
     free_workspace(ctx);
     hipError_t e = hipSuccess;
-    if ((e = hipMalloc(&ctx->A, kNumPrimes * L * sizeof(uint32_t))) != hipSuccess ||
-        (e = hipMalloc(&ctx->B, kNumPrimes * L * sizeof(uint32_t))) != hipSuccess ||
+    if ((e = hipMalloc(&ctx->A, elems * sizeof(uint32_t))) != hipSuccess ||
+        (e = hipMalloc(&ctx->B, elems * sizeof(uint32_t))) != hipSuccess ||
         (e = hipMalloc(&ctx->status, std::max<uint64_t>(status_words(D), 1) * sizeof(uint32_t))) != hipSuccess) {
         free_workspace(ctx);
         return fail(ctx, PA_ENOMEM, "workspace allocation", e);
     }
-    ctx->cap_L = L;
+    ctx->cap_L = elems;
     ctx->cap_D = D;
     return PA_OK;
 }
 
-int ensure_workspace(pa_ctx* ctx, uint64_t n) { return ensure_caps(ctx, len_of(n), digits_of(n)); }
+int ensure_workspace(pa_ctx* ctx, uint64_t n) { return ensure_caps(ctx, arr_elems(n), digits_of(n)); }
 
 int ensure_staging(pa_ctx* ctx, uint64_t words, bool operands)
 {
@@ -257,6 +289,7 @@ struct Recorder {
 // Transform plan for L = f 2^k: tile size, passes, register steps, output scale.
 struct Plan {
     int f = 1, k = 0, t = 0, ts = 0, P = 0;
+    int W = 2;                         // digit words: 2W + 1 primes
     uint64_t L = 0;
     int r[8] = {}, s[8] = {}, logC[8] = {};
     int nsteps[8] = {};
@@ -274,6 +307,7 @@ bool make_plan(Len len, Plan* pl, unsigned blocks = 1, PlanParams pp = {})
 {
     pl->f = len.f;
     pl->k = len.k;
+    pl->W = len.W;
     pl->L = len.L();
     const int t = pp.t ? pp.t : plan_tile(len.k + (len.f == 3 ? 2 : 0), blocks);
     // strided tiles: one size up for the factor-3 pass of long transforms
@@ -329,7 +363,7 @@ bool make_plan(Len len, Plan* pl, unsigned blocks = 1, PlanParams pp = {})
 }
 
 // Index of a transform length in the context's table of chosen plans.
-int len_slot(Len len) { return (len.f == 3 ? 32 : 0) + len.k; }
+int len_slot(Len len) { return (len.W == 3 ? 64 : 0) + (len.f == 3 ? 32 : 0) + len.k; }
 
 // The plan a context uses for length len: its tuned or set geometry, else the
 // defaults.
@@ -392,8 +426,9 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
 {
     const unsigned batch = w.batch;
     const uint64_t L = pl.L;
-    const uint64_t arr = batch * kNumPrimes * 4ull * L;    // residue arrays, all blocks
-    const uint64_t outD = kNumPrimes * 4ull * w.coeffs;    // product coefficients kept
+    const int NP = 2 * pl.W + 1;                           // primes of the layout
+    const uint64_t arr = batch * NP * 4ull * L;            // residue arrays, all blocks
+    const uint64_t outD = NP * 4ull * w.coeffs;            // product coefficients kept
     const int P = pl.P;
 
     PassArgs base{};
@@ -403,8 +438,10 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     base.tb = Tables{ctx->pass_lo, ctx->pass_hi};
     base.store_limit = (uint32_t)L;
     base.jobs = w.jobs;
+    base.primes = NP;
+    base.dwords = pl.W;
     auto geometry = [&](PassArgs& a, int i) { pass_geometry(a, pl, i); };
-    const uint32_t limit = (uint32_t)((coeffs_of(w.n) + 3) & ~3ull);
+    const uint32_t limit = (uint32_t)((coeffs_of(w.n, pl.W) + 3) & ~3ull);
 
     // The first passes of c and of x share their geometry and are independent:
     // one launch runs both (grid.z = 2), so each fills the other's last wave.
@@ -483,6 +520,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     CarryArgs ca{};
     ca.res = w.B;
     ca.L = (uint32_t)L;
+    ca.dwords = pl.W;
     ca.num_digits = (uint32_t)digits_of(w.n);
     ca.n = w.n;
     ca.m = w.m;
@@ -500,7 +538,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     ca.jobs = w.jobs;
     const uint64_t chunk_bytes = 4ull * w.chunks * batch;
     PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + chunk_bytes, launch_carry_local(ca, stream, batch, ev_));
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, kNumPrimes * 4ull * w.window + chunk_bytes + w.out_bytes,
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, NP * 4ull * w.window + chunk_bytes + w.out_bytes,
               launch_carry_apply(ca, stream, batch, ev_));
     return PA_OK;
 }
@@ -527,11 +565,11 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     w.B = ctx->B;
     w.carry = ctx->status;
     w.out = d_out;
-    w.chunks = chunks_of(digits_of(n));
-    w.per = carry_digits_per_thread((uint32_t)digits_of(n));
+    w.chunks = chunks_of(digits_of(n), pl.W);
+    w.per = carry_digits_per_thread((uint32_t)digits_of(n), pl.W);
     w.key_bytes = (n + 7) / 8;
-    w.coeffs = coeffs_of(n);
-    w.window = window_coeffs(n, m);
+    w.coeffs = coeffs_of(n, pl.W);
+    w.window = window_coeffs(n, m, pl.W);
     w.out_bytes = words_of(m) * 8;
     return enqueue_plan(ctx, pl, w, stream, rec);
 }
@@ -542,14 +580,12 @@ namespace pa {
 
 uint64_t block_workspace_bytes(uint64_t n)
 {
-    const uint64_t L = len_of(n);
-    return 2 * ((kNumPrimes * 4ull * L + 255) & ~255ull) + ((4ull * status_words(digits_of(n)) + 255) & ~255ull);
+    return 2 * ((4ull * arr_elems(n) + 255) & ~255ull) + ((4ull * status_words(digits_of(n)) + 255) & ~255ull);
 }
 
 void block_layout(uint64_t n, uint8_t* base, BlockBufs* b)
 {
-    const uint64_t L = len_of(n);
-    const uint64_t arr = (kNumPrimes * 4ull * L + 255) & ~255ull;
+    const uint64_t arr = (4ull * arr_elems(n) + 255) & ~255ull;
     b->A = reinterpret_cast<uint32_t*>(base);
     b->B = reinterpret_cast<uint32_t*>(base + arr);
     b->carry = reinterpret_cast<uint32_t*>(base + 2 * arr);
@@ -571,11 +607,11 @@ int enqueue_block(pa_ctx* ctx, const BlockBufs& b, hipStream_t stream)
     w.B = b.B;
     w.carry = b.carry;
     w.out = b.out;
-    w.chunks = chunks_of(digits_of(b.n));
-    w.per = carry_digits_per_thread((uint32_t)digits_of(b.n));
+    w.chunks = chunks_of(digits_of(b.n), pl.W);
+    w.per = carry_digits_per_thread((uint32_t)digits_of(b.n), pl.W);
     w.key_bytes = (b.n + 7) / 8;
-    w.coeffs = coeffs_of(b.n);
-    w.window = window_coeffs(b.n, b.m);
+    w.coeffs = coeffs_of(b.n, pl.W);
+    w.window = window_coeffs(b.n, b.m, pl.W);
     w.out_bytes = words_of(b.m) * 8;
     return enqueue_plan(ctx, pl, w, stream);
 }
@@ -678,7 +714,7 @@ int enqueue_toeplitz(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* d_t, ui
     Plan pl;
     if (!plan_for(ctx, tp.len, &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     const uint64_t L = pl.L;
-    int rc = ensure_caps(ctx, (L + kNumPrimes - 1) / kNumPrimes, 0);
+    int rc = ensure_caps(ctx, L, 0);
     if (rc) return rc;
     const int P = pl.P;
     PassArgs base{};
@@ -857,9 +893,8 @@ uint64_t pa_transform_length(uint64_t n)
 uint64_t pa_workspace_bytes(uint64_t n)
 {
     if (n == 0 || n > PA_MAX_N) return 0;
-    const uint64_t L = len_of(n);
     const uint64_t D = digits_of(n);
-    return 2 * kNumPrimes * L * 4 + status_words(D) * 4;
+    return 2 * arr_elems(n) * 4 + status_words(D) * 4;
 }
 
 int pa_init(pa_ctx** out, int device)
@@ -897,14 +932,15 @@ int pa_init(pa_ctx** out, int device)
         if (!h_lo || !h_hi) { rc = PA_ENOMEM; break; }
         for (int pi = 0; pi < kNumPrimes; ++pi) {
             const uint64_t p = kPrimes[pi];
-            const uint64_t wo = kRoot[pi];                                 // order 3 2^25
+            // w^E for the order-3 2^25 root w; a prime whose root r has order
+            // 3 2^22 stores r^(E / 8), defined for the multiples of 8 that
+            // its transforms use (other low entries stay 0)
+            const uint64_t wo = kRoot[pi];
+            const int sh = kRootShift[pi];
+            for (int i = 0; i < 4096; ++i)
+                h_lo[pi * 4096 + i] = (i & ((1 << sh) - 1)) ? 0u : hmont(hpow(wo, (uint64_t)(i >> sh), p), p);
+            const uint64_t step = hpow(wo, 4096u >> sh, p);
             uint64_t w = 1;
-            for (int i = 0; i < 4096; ++i) {
-                h_lo[pi * 4096 + i] = hmont(w, p);
-                w = w * wo % p;
-            }
-            const uint64_t step = hpow(wo, 4096, p);
-            w = 1;
             for (int j = 0; j < kRootHi; ++j) {
                 h_hi[pi * kRootHi + j] = hmont(w, p);
                 w = w * step % p;
@@ -1073,7 +1109,7 @@ int pa_mul_create(pa_ctx* ctx, uint64_t seed_a, const uint64_t* d_c, uint64_t n,
     mh->A = nullptr;
     mh->plan = pl;
     const uint64_t L = pl.L;
-    hipError_t e = hipMalloc(&mh->A, kNumPrimes * 4ull * L);
+    hipError_t e = hipMalloc(&mh->A, (2ull * pl.W + 1) * 4ull * L);
     if (e != hipSuccess) {
         delete mh;
         return fail(ctx, PA_ENOMEM, "multiplier spectrum allocation", e);
@@ -1086,7 +1122,7 @@ int pa_mul_create(pa_ctx* ctx, uint64_t seed_a, const uint64_t* d_c, uint64_t n,
     w.A = mh->A;
     w.only_chat = true;
     w.key_bytes = (n + 7) / 8;
-    w.coeffs = coeffs_of(n);
+    w.coeffs = coeffs_of(n, pl.W);
     rc = enqueue_plan(ctx, pl, w, (hipStream_t)stream);
     if (rc) {
         (void)hipFree(mh->A);
@@ -1118,11 +1154,11 @@ int pa_hash_mul_async(pa_ctx* ctx, const pa_mul* mh, const uint64_t* d_key, uint
     w.B = ctx->B;
     w.carry = ctx->status;
     w.out = d_out;
-    w.chunks = chunks_of(digits_of(n));
-    w.per = carry_digits_per_thread((uint32_t)digits_of(n));
+    w.chunks = chunks_of(digits_of(n), pl.W);
+    w.per = carry_digits_per_thread((uint32_t)digits_of(n), pl.W);
     w.key_bytes = (n + 7) / 8;
-    w.coeffs = coeffs_of(n);
-    w.window = window_coeffs(n, m);
+    w.coeffs = coeffs_of(n, pl.W);
+    w.window = window_coeffs(n, m, pl.W);
     w.out_bytes = words_of(m) * 8;
     w.have_chat = true;
     return enqueue_plan(ctx, pl, w, (hipStream_t)stream);
@@ -1178,7 +1214,7 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
     }
     if (ok.empty()) return fail(ctx, PA_EINVAL, "no valid block in the batch");
     std::stable_sort(ok.begin(), ok.end(), [&](size_t a, size_t b) {
-        return len_of(jobs[a].n) < len_of(jobs[b].n);
+        return layout_key(jobs[a].n) < layout_key(jobs[b].n);
     });
     pa_batch* b = new (std::nothrow) pa_batch;
     if (!b) return PA_ENOMEM;
@@ -1189,10 +1225,10 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
     std::vector<uint64_t> offA(ok.size()), offC(ok.size());
     uint64_t bytes = 0;
     for (size_t i = 0; i < ok.size();) {
-        const uint64_t Lg = len_of(jobs[ok[i]].n);
+        const uint64_t key = layout_key(jobs[ok[i]].n);
         size_t e = i;
         uint64_t maxD = 0;
-        while (e < ok.size() && len_of(jobs[ok[e]].n) == Lg) {
+        while (e < ok.size() && layout_key(jobs[ok[e]].n) == key) {
             maxD = std::max<uint64_t>(maxD, digits_of(jobs[ok[e]].n));
             ++e;
         }
@@ -1203,9 +1239,10 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
         }
         g.first = (uint32_t)i;
         g.count = (uint32_t)(e - i);
-        g.per = carry_digits_per_thread((uint32_t)maxD);
+        const int W = g.plan.W;
+        g.per = carry_digits_per_thread((uint32_t)maxD, W);
         const uint64_t chunk = (uint64_t)kCarryThreads * g.per;
-        const uint64_t L = Lg;
+        const uint64_t arr = align256((2ull * W + 1) * 4ull * g.plan.L);
         for (size_t k = i; k < e; ++k) {
             const pa_job& j = jobs[ok[k]];
             const uint64_t D = digits_of(j.n);
@@ -1222,11 +1259,11 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
             d.out = j.out;
             g.chunks = std::max(g.chunks, d.chunks);
             g.key_bytes += (j.n + 7) / 8;
-            g.coeffs += coeffs_of(j.n);
-            g.window += window_coeffs(j.n, j.m);
+            g.coeffs += coeffs_of(j.n, W);
+            g.window += window_coeffs(j.n, j.m, W);
             g.out_bytes += words_of(j.m) * 8;
             offA[k] = bytes;
-            bytes += 2 * align256(kNumPrimes * 4ull * L);
+            bytes += 2 * arr;
             offC[k] = bytes;
             bytes += align256(8ull * d.chunks);
         }
@@ -1243,9 +1280,8 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
     }
     b->ws_bytes = bytes;
     for (size_t k = 0; k < h.size(); ++k) {
-        const uint64_t L = len_of(h[k].n);
         h[k].A = reinterpret_cast<uint32_t*>(b->ws + offA[k]);
-        h[k].B = reinterpret_cast<uint32_t*>(b->ws + offA[k] + align256(kNumPrimes * 4ull * L));
+        h[k].B = reinterpret_cast<uint32_t*>(b->ws + offA[k] + align256(4ull * arr_elems(h[k].n)));
         h[k].carry = reinterpret_cast<uint32_t*>(b->ws + offC[k]);
     }
     if ((e = hipMemcpy(b->d_jobs, h.data(), sizeof(JobDesc) * h.size(), hipMemcpyHostToDevice)) !=

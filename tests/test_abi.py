@@ -34,16 +34,17 @@ def test_library_exports_every_declared_symbol():
 
 def test_host_helpers():
     import paper_1910_04429_amd as pa
-    # L = smallest 2^k (k >= 6) or, from 2^18 on, 3 * 2^k with L >= 2D - 1,
-    # D = ceil(n / 64) digits of 64 bits
+    # L = smallest 2^k (k >= 6) or, from 2^18 on, 3 * 2^k with L >= 2D - 1, for
+    # D = ceil(n / 64) digits over five primes or D = ceil(n / 96) over seven,
+    # whichever needs less transform work
     assert pa.pa_transform_length(1) == 64
-    assert pa.pa_transform_length(1_000_000) == 1 << 15        # 2D - 1 = 31249
-    assert pa.pa_transform_length(10_000_000) == 3 << 17       # 312499
-    assert pa.pa_transform_length(100_000_000) == 3 << 20      # 3124999
-    assert pa.pa_transform_length(pa.PA_MAX_N) == 1 << 24      # 2^24 - 1
+    assert pa.pa_transform_length(1_000_000) == 1 << 15        # 64-bit: 2D - 1 = 31249
+    assert pa.pa_transform_length(10_000_000) == 1 << 18       # 96-bit: 208333
+    assert pa.pa_transform_length(100_000_000) == 1 << 21      # 96-bit: 2083333
+    assert pa.pa_transform_length(pa.PA_MAX_N) == 1 << 24      # 64-bit: 2^24 - 1
     assert pa.pa_transform_length(pa.PA_MAX_N + 1) == 0
     assert pa.pa_transform_length(0) == 0
-    assert pa.pa_workspace_bytes(100_000_000) >= 2 * 5 * 4 * (3 << 20)
+    assert pa.pa_workspace_bytes(100_000_000) >= 2 * 7 * 4 * (1 << 21)
     assert pa.pa_strerror(pa.PA_EINVAL) == "invalid argument"
 
 

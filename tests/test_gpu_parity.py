@@ -40,7 +40,9 @@ def _rand_words(rng, n):
 RAGGED = [(1, 1), (2, 1), (31, 7), (32, 32), (33, 1), (63, 63), (64, 1), (65, 64),
           (100, 99), (1000, 3), (2047, 2047), (4095, 1000), (65_536, 12_345),
           (131_071, 65_537), (131_072, 131_072), (131_073, 1), (262_145, 100_000),
-          (1_000_003, 99_999), (3_000_000, 1_500_001), (4_194_305, 64)]
+          (1_000_003, 99_999), (3_000_000, 1_500_001), (4_194_305, 64),
+          # sizes whose transform uses 96-bit digits over seven primes
+          (3_000_001, 3), (6_000_011, 2_999_999), (8_388_609, 4_000_000)]
 
 
 @pytest.mark.parametrize("n,m", RAGGED)
@@ -64,7 +66,8 @@ def _words(v, n):
     return np.frombuffer((v & ((1 << (64 * w)) - 1)).to_bytes(8 * w, "little"), dtype="<u8").copy()
 
 
-@pytest.mark.parametrize("n,m", [(64, 64), (4097, 2000), (200_001, 77_777), (2_000_000, 1_000_000)])
+@pytest.mark.parametrize("n,m", [(64, 64), (4097, 2000), (200_001, 77_777), (2_000_000, 1_000_000),
+                                 (5_000_001, 1_000_000)])
 def test_explicit_operands_and_special_keys(pa, ctx, n, m):
     _log(f"explicit n={n} m={m}")
     rng = np.random.default_rng(n)

@@ -126,9 +126,11 @@ def test_cached_multiplier_keeps_its_geometry(pa, ctx):
 
 
 def test_invalid_geometry_is_rejected(pa, ctx):
-    for bad in [{"tile_log": 15}, {"tile_log": 14, "strided_tile_log": 3},
-                {"tile_log": 14, "strided_tile_log": 14, "rows3_log": 12}]:
+    # n = 8 388 609 has a 3 * 2^16 transform: with 2^14 tiles its factor-3 pass
+    # has at most 2^2 rows, so rows3_log 12 does not fit
+    for n, bad in [(10**8, {"tile_log": 15}), (10**8, {"tile_log": 14, "strided_tile_log": 3}),
+                   (8_388_609, {"tile_log": 14, "strided_tile_log": 14, "rows3_log": 12})]:
         with pytest.raises(pa.PAError) as e:
-            pa.pa_plan_set(ctx, 10**8, bad)
+            pa.pa_plan_set(ctx, n, bad)
         assert e.value.status == pa.PA_EINVAL
-    assert pa.pa_plan_get(ctx, 10**8) == pa.pa_plan_candidates(10**8)[0]
+        assert pa.pa_plan_get(ctx, n) == pa.pa_plan_candidates(n)[0]

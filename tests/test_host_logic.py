@@ -101,25 +101,39 @@ def test_arena_first_fit_and_merge(arena_bin):
     assert out[6] == "ok 0"
 
 
+def _shortest_length(need):
+    """Smallest 2^k (k >= 6) >= need, or, from 2^18 on, 3 * 2^(k-2) when that fits."""
+    k = max(6, (need - 1).bit_length())
+    if k >= 18 and 3 << (k - 2) >= need:
+        return 3 << (k - 2)
+    return 1 << k
+
+
 def test_plan_lengths_cover_the_linear_convolution():
-    """L >= 2D - 1 (no wrap into the low digits), L = 2^k or 3 * 2^k dividing
-    3 * 2^25, and no shorter length of either form would do."""
+    """The layout with less transform work (primes x L x log2 L) among 64-bit
+    digits over five primes and 96-bit digits over seven (those up to
+    L = 3 * 2^22), each with the shortest L >= 2D - 1 of the form 2^k or 3 * 2^k."""
+    import math
     import paper_1910_04429_amd as pa
     order = 3 << 25
-    for n in [1, 63, 64, 65, 1000, 65_536, 1_000_000, 6_291_400, 6_400_000, 10**7, 10**8,
-              pa.PA_MAX_N] + [int(x) for x in np.geomspace(1e5, pa.PA_MAX_N, 40)]:
-        L = pa.pa_transform_length(n)
-        D = (n + 63) // 64
-        need = 2 * D - 1
-        assert L >= need and order % L == 0 and L <= 1 << 25
-        f = 3 if L % 3 == 0 else 1
-        assert (L // f) & (L // f - 1) == 0
-        pow2 = 1 << max(6, (need - 1).bit_length())
-        assert L <= pow2
-        if f == 1 and pow2 >= 1 << 18:
-            assert 3 * pow2 // 4 < need           # the 3 * 2^k length would not fit
-        assert pa.pa_workspace_bytes(n) >= 2 * 5 * 4 * L
-    assert pa.pa_transform_length(10**8) == 3 << 20
+    seen = set()
+    for n in [1, 63, 64, 65, 1000, 65_536, 1_000_000, 5_000_000, 6_291_400, 6_400_000, 10**7,
+              3 * 10**7, 10**8, 2 * 10**8, pa.PA_MAX_N] + \
+            [int(x) for x in np.geomspace(1e5, pa.PA_MAX_N, 40)]:
+        cands = []
+        for W, P, lmax in [(2, 5, order), (3, 7, 3 << 22)]:
+            D = (n + 32 * W - 1) // (32 * W)
+            L = _shortest_length(2 * D - 1)
+            assert L >= 2 * D - 1 and order % L == 0
+            if L <= lmax:
+                cands.append((P * L * math.log2(L), W, P, L))
+        work, W, P, L = min(cands, key=lambda c: (c[0], c[1]))
+        assert pa.pa_transform_length(n) == L, n
+        assert pa.pa_workspace_bytes(n) >= 2 * P * 4 * L
+        seen.add(W)
+    assert seen == {2, 3}
+    assert pa.pa_transform_length(10**6) == 1 << 15        # 64-bit digits, five primes
+    assert pa.pa_transform_length(10**8) == 1 << 21        # 96-bit digits, seven primes
 
 
 def _write_counter_csv(d, counter, rows):
@@ -187,9 +201,9 @@ def test_plan_candidates_default_first_and_valid():
     import paper_1910_04429_amd as pa
     c8 = pa.pa_plan_candidates(10**8)
     assert (c8[0]["tile_log"], c8[0]["strided_tile_log"], c8[0]["rows3_log"], c8[0]["passes"]) \
-        == (12, 13, 8, 2)
+        == (12, 12, 0, 2)
     keys = {(c["tile_log"], c["strided_tile_log"], c["rows3_log"]) for c in c8}
-    assert (13, 13, 7) in keys and (14, 14, 6) in keys and len(keys) == len(c8)
+    assert (13, 13, 0) in keys and (14, 14, 0) in keys and len(keys) == len(c8)
     assert all(2 <= c["passes"] <= 3 for c in c8)
     small = pa.pa_plan_candidates(1000)
     assert small and all(c["passes"] == 1 for c in small)
