@@ -90,9 +90,10 @@ __device__ __forceinline__ void crt(const uint32_t (&r)[NP], uint32_t (&z)[NP])
         uint32_t t = r[i];
 #pragma unroll
         for (int j = 0; j < i; ++j) {
-            // v_j < p_j < 2 p_i (every prime is above 2^30)
+            // v_j < p_j < 2 p_i (every prime is above 2^30): reduce it, then
+            // t + p - v_j < 2 p < 2^32 goes into Shoup's multiply unreduced
             const uint32_t vj = (kPrimes[j] > p) ? min(v[j], v[j] - p) : v[j];
-            t = fmul_mont(fsub(t, vj, p), kGarner.inv[i][j], p, kNegInv[i]);
+            t = fmul_shoup(t + p - vj, kGarner.inv[i][j], kGarner.q[i][j], p);
         }
         v[i] = t;
     }

@@ -112,16 +112,19 @@ constexpr uint32_t shoup_quotient(uint64_t w, uint64_t p) { return (uint32_t)((w
 // Garner's mixed-radix CRT over the first P primes: with v_0 = r_0 and
 //   v_i = (...((r_i - v_0) p_0^{-1} - v_1) p_1^{-1} ... - v_{i-1}) p_{i-1}^{-1}  mod p_i,
 // the coefficient is v_0 + p_0 (v_1 + p_1 (v_2 + ... + p_{P-2} v_{P-1})).
-// kGarner[i][j] is p_j^{-1} mod p_i in Montgomery form (j < i).
+// kGarner.inv[i][j] is p_j^{-1} mod p_i (j < i) and q[i][j] its Shoup quotient.
 struct GarnerTable {
     uint32_t inv[kNumPrimes][kNumPrimes];
+    uint32_t q[kNumPrimes][kNumPrimes];
 };
 constexpr GarnerTable make_garner()
 {
     GarnerTable t{};
     for (int i = 0; i < kNumPrimes; ++i)
-        for (int j = 0; j < i; ++j)
-            t.inv[i][j] = to_mont(inv_mod(kPrimes[j] % kPrimes[i], kPrimes[i]), kPrimes[i]);
+        for (int j = 0; j < i; ++j) {
+            t.inv[i][j] = inv_mod(kPrimes[j] % kPrimes[i], kPrimes[i]);
+            t.q[i][j] = shoup_quotient(t.inv[i][j], kPrimes[i]);
+        }
     return t;
 }
 constexpr GarnerTable kGarner = make_garner();
