@@ -197,7 +197,7 @@ def time_single(pa, ctx, torch, blk, steps, warmup, plan=None):
     context's transform geometry for this length is autotuned first, unless
     a plan is given)."""
     if plan is None:
-        pa.pa_tune(ctx, blk.n, 3)
+        pa.pa_tune(ctx, blk.n, 8)
     else:
         pa.pa_plan_set(ctx, blk.n, plan)
     d_key = torch.from_numpy(blk.key().view(np.int64)).cuda()

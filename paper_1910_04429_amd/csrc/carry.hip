@@ -52,6 +52,18 @@ __device__ __forceinline__ uint32_t compose(uint32_t f, uint32_t g)
 
 __device__ __forceinline__ uint32_t apply(uint32_t f, uint32_t c) { return (f >> (2 * c)) & 3u; }
 
+// Inclusive scan of one function per lane over a wavefront, in lane order.
+__device__ __forceinline__ uint32_t wave_scan(uint32_t f, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t prev = __shfl_up(f, d);
+        if (lane >= d)
+            f = compose(prev, f);
+    }
+    return f;
+}
+
 __device__ __forceinline__ uint32_t digit_function(uint64_t s)
 {
     uint32_t f = 0;
@@ -175,7 +187,6 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     constexpr int kChunk = kCarryThreads * kPer;
     constexpr int kSlots = kChunk + 2 + (kChunk + 2) / kPer + 1;
     __shared__ uint32_t val[kSlots];
-    __shared__ uint32_t scan[kCarryThreads];
 
     const int tid = threadIdx.x;
     const uint32_t chunk = blockIdx.x;
@@ -302,45 +313,51 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     for (int i = 0; i < kPer; ++i)
         f = compose(f, digit_function(s[i]));
 
-    // inclusive scan of the thread functions in thread order
-    scan[tid] = f;
+    // inclusive scan of the thread functions in thread order: within each
+    // wavefront by lane shuffles, then across the four wavefronts through LDS
+    const int lane = tid & 63, wave = tid >> 6;
+    f = wave_scan(f, lane);
+    __shared__ uint32_t wtot[kCarryThreads / 64];
+    if (lane == 63)
+        wtot[wave] = f;
     __syncthreads();
-    for (int d = 1; d < kCarryThreads; d <<= 1) {
-        const uint32_t prev = (tid >= d) ? scan[tid - d] : kIdentity;
-        __syncthreads();
-        f = compose(prev, f);
-        scan[tid] = f;
-        __syncthreads();
-    }
+    uint32_t before = kIdentity;              // the wavefronts before this one
+    for (int w = 0; w < wave; ++w)
+        before = compose(before, wtot[w]);
 
     if (!kApply) {
         if (tid == kCarryThreads - 1)
-            a.desc[chunk] = f;
+            a.desc[chunk] = compose(before, f);
         return;
     }
     // carry entering this chunk: the functions of chunks 0 .. chunk-1 (written
     // by the local kernel) composed in order and applied to carry 0; each
     // workgroup reads the few thousand bytes itself instead of waiting for a
     // separate scan launch
-    __shared__ uint32_t pre[kCarryThreads];
+    __shared__ uint32_t wpre[kCarryThreads / 64];
+    uint32_t cin_chunk;
     {
         const uint32_t per_t = (chunk + kCarryThreads - 1) / kCarryThreads;
         const uint32_t lo = (uint32_t)tid * per_t;
         uint32_t g = kIdentity;
         for (uint32_t k = lo; k < lo + per_t && k < chunk; ++k)
             g = compose(g, a.desc[k]);
-        pre[tid] = g;
+        g = wave_scan(g, lane);
+        if (lane == 63)
+            wpre[wave] = g;
         __syncthreads();
-        for (int d = 1; d < kCarryThreads; d <<= 1) {
-            if ((tid & (2 * d - 1)) == 0)
-                pre[tid] = compose(pre[tid], pre[tid + d]);
-            __syncthreads();
-        }
+        uint32_t all = kIdentity;
+#pragma unroll
+        for (int w = 0; w < kCarryThreads / 64; ++w)
+            all = compose(all, wpre[w]);
+        cin_chunk = apply(all, 0u);
     }
-    const uint32_t cin_chunk = apply(pre[0], 0u);
 
     // resolve this thread's digits; V digits of the chunk (and two past it) to LDS
-    uint64_t carry = tid ? apply(scan[tid - 1], cin_chunk) : cin_chunk;
+    uint32_t excl = __shfl_up(f, 1);          // inclusive scan of the lane before
+    if (lane == 0)
+        excl = kIdentity;
+    uint64_t carry = apply(compose(before, excl), cin_chunk);
     const uint32_t top = (uint32_t)(a.n & 31);
 #pragma unroll
     for (int i = 0; i < kPer + kExtra; ++i) {
