@@ -21,9 +21,9 @@ constexpr int kLogMaxLen = 25;                 // min 2-adicity of the first fiv
 // (quotients 20, 18, 21, 17 and 11), so they have such a root and serve every
 // length 2^k and 3 * 2^k up to kOrder.  The last two only have roots of order
 // kOrder / 8 = 3 * 2^22: their root r stands for w^8, exponent E of w is power
-// E / 8 of r, which is exact for every length up to 3 * 2^22 (all exponents
-// used are then multiples of 8).  They serve the 96-bit-digit layout only,
-// whose transforms stay within that length.
+// E / 8 of r, which is exact for every length L that divides 3 * 2^22 (all
+// exponents used are multiples of kOrder / L, hence of 8).  They serve the
+// 96-bit-digit layout only, whose transform lengths divide that order.
 constexpr uint32_t kOrder = 3u << kLogMaxLen;
 constexpr uint32_t kPrimes[kNumPrimes] = {
     2013265921u,  // 15 * 2^27 + 1
@@ -36,9 +36,10 @@ constexpr uint32_t kPrimes[kNumPrimes] = {
 };
 // log2 of kOrder / (order of the prime's root): 0 or 3.
 constexpr int kRootShift[kNumPrimes] = {0, 0, 0, 0, 0, 3, 3};
-// Longest transform of each layout (W = 2: five primes; W = 3: seven).
-constexpr uint32_t kMaxLen64 = kOrder;
-constexpr uint32_t kMaxLen96 = kOrder >> 3;
+// Every transform length of the seven-prime (96-bit digit) layout divides
+// this; the five-prime layout's divide kOrder.  (2^23 <= 3 * 2^22 does not
+// divide it: at L = 2^23 the exponent unit kOrder / L is 12.)
+constexpr uint32_t kOrder96 = kOrder >> 3;
 
 // -p^{-1} mod 2^32 by Newton iteration (each step doubles the correct bits).
 constexpr uint32_t neg_inverse_u32(uint32_t p)

@@ -82,7 +82,7 @@ Len len_for(uint64_t need)
 
 // Layout and length for an n-bit block: of 64-bit digits over five primes and
 // 96-bit digits over seven, the one with less transform work, primes x L x
-// log2 L (96-bit digits only up to their longest transform, 3 2^22).  At
+// log2 L (96-bit digits only for lengths that divide 3 2^22).  At
 // n = 10^8: 5 x 3 2^20 against 7 x 2^21, the second; at 10^6: 5 x 2^15 against
 // 7 x 2^15, the first.
 Len plan_len(uint64_t n)
@@ -90,7 +90,7 @@ Len plan_len(uint64_t n)
     Len a = len_for(2 * coeffs_of(n, 2) - 1);
     Len b = len_for(2 * coeffs_of(n, 3) - 1);
     b.W = 3;
-    if (b.L() > kMaxLen96) return a;
+    if (kOrder96 % b.L() != 0) return a;
     auto work = [](const Len& x) {
         return (double)x.primes() * (double)x.L() * (x.k + (x.f == 3 ? 1.585 : 0.0));
     };

@@ -144,6 +144,24 @@ def test_workload_blocks_device_path(pa, ctx, name):
     assert np.array_equal(got, want)
 
 
+def test_largest_seven_prime_transform_closed_forms(pa, ctx):
+    """n = 301 989 888: 96-bit digits, D = 3 * 2^20, the longest transform of the
+    seven-prime layout (3 * 2^21); closed forms that hold at any size."""
+    n = 301_989_888
+    assert pa.pa_transform_length(n) == 3 << 21
+    m = n // 5 + 3
+    mask = (1 << n) - 1
+    sa, sb = 4321, 8765
+    c = _int(oracle.expand_operand(sa, n, True))
+    d = _int(oracle.expand_operand(sb, n, False))
+    top = lambda v: _words((v & mask) >> (n - m), m)
+    for name, x, v in [("one", 1, c + d), ("shift", 1 << (n - 9), (c << (n - 9)) + d),
+                       ("all_ones", mask, d - c)]:
+        _log(f"largest seven-prime transform key={name}")
+        got = pa.pa_hash(ctx, _words(x, n), sa, sb, n, m)
+        assert np.array_equal(got, top(v)), name
+
+
 def test_maximum_size_closed_forms(pa, ctx):
     """n = PA_MAX_N (transform length 2^25): closed forms that hold at any size."""
     n = pa.PA_MAX_N

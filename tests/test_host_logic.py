@@ -111,21 +111,23 @@ def _shortest_length(need):
 
 def test_plan_lengths_cover_the_linear_convolution():
     """The layout with less transform work (primes x L x log2 L) among 64-bit
-    digits over five primes and 96-bit digits over seven (those up to
-    L = 3 * 2^22), each with the shortest L >= 2D - 1 of the form 2^k or 3 * 2^k."""
+    digits over five primes and 96-bit digits over seven (only lengths that
+    divide 3 * 2^22, the order of the last two primes' roots), each with the
+    shortest L >= 2D - 1 of the form 2^k or 3 * 2^k."""
     import math
     import paper_1910_04429_amd as pa
     order = 3 << 25
     seen = set()
     for n in [1, 63, 64, 65, 1000, 65_536, 1_000_000, 5_000_000, 6_291_400, 6_400_000, 10**7,
-              3 * 10**7, 10**8, 2 * 10**8, pa.PA_MAX_N] + \
+              3 * 10**7, 10**8, 2 * 10**8, 301_989_888, 301_989_889, 350_000_000, 402_653_184,
+              pa.PA_MAX_N] + \
             [int(x) for x in np.geomspace(1e5, pa.PA_MAX_N, 40)]:
         cands = []
-        for W, P, lmax in [(2, 5, order), (3, 7, 3 << 22)]:
+        for W, P, root_order in [(2, 5, order), (3, 7, 3 << 22)]:
             D = (n + 32 * W - 1) // (32 * W)
             L = _shortest_length(2 * D - 1)
             assert L >= 2 * D - 1 and order % L == 0
-            if L <= lmax:
+            if root_order % L == 0:
                 cands.append((P * L * math.log2(L), W, P, L))
         work, W, P, L = min(cands, key=lambda c: (c[0], c[1]))
         assert pa.pa_transform_length(n) == L, n
@@ -134,6 +136,10 @@ def test_plan_lengths_cover_the_linear_convolution():
     assert seen == {2, 3}
     assert pa.pa_transform_length(10**6) == 1 << 15        # 64-bit digits, five primes
     assert pa.pa_transform_length(10**8) == 1 << 21        # 96-bit digits, seven primes
+    # the largest seven-prime transform; 2^23 (n up to 402 653 184 with 96-bit
+    # digits) does not divide 3 * 2^22, so those blocks take 64-bit digits
+    assert pa.pa_transform_length(301_989_888) == 3 << 21
+    assert pa.pa_transform_length(350_000_000) == 3 << 22
 
 
 def _write_counter_csv(d, counter, rows):
