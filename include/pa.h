@@ -11,7 +11,9 @@
  * reduction mod 2^n (3.2.3), export (3.2.4) and selection of the most
  * significant r = m bits (3.2.5).  x is the n-bit corrected key, the output is
  * the m-bit final key.  The large multiply is an exact NTT convolution (the
- * approach of Alg. 1) over three 31-bit primes, done by HIP kernels.
+ * approach of Alg. 1) of 64-bit digits over five 31-bit primes or 96-bit
+ * digits over seven, whichever needs less transform work for the block, done
+ * by HIP kernels.
  *
  * Bit layout (all arrays): little-endian 64-bit words, word 0 least
  * significant; bit i of a value is bit (i % 64) of word i / 64.  Inputs have
@@ -51,8 +53,8 @@ enum pa_status {
     PA_ENODEV = 4,   /* no usable gfx950 device with that index */
 };
 
-/* Largest block: 2^24 32-bit digits (transform length 2^25, the smallest
- * 2-adicity of the three primes). */
+/* Largest block: 2^23 64-bit digits (transform length 2^24; the coefficient
+ * bound 2^23 2^128 stays below the five primes' product, 2^153.4). */
 #define PA_MAX_N ((uint64_t)1 << 29)
 
 typedef struct pa_ctx pa_ctx;
