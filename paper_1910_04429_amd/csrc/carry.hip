@@ -14,9 +14,8 @@
 //
 // with carry_0 = 0 and every carry in [0, 3].  Digits k >= D = ceil(n/32) are
 // discarded (mod 2^n), the top digit is masked to n bits, and bits [n - m, n)
-// of V are the output.  The chain is a scan of carry-transfer functions
-// f_k : {0..3} -> {0..3}, f_k(c) = (s_k + c) >> 32, packed 2 bits per input in
-// one byte; composition is associative.
+// of V are the output.  The chain is a scan of the carry-transfer functions
+// f_k(c) = (s_k + c) >> 32 of carryfn.h; composition is associative.
 //
 // Two launches, none of which waits on another workgroup: (1) every chunk of
 // digits loads its threads' residues, forms its column sums and scans its
@@ -25,12 +24,11 @@
 // carry-in, redoes (1), resolves its digits (and two past its end) and writes
 // every output word that starts inside the chunk.  Workgroups on different
 // XCDs never exchange data inside a kernel.
+#include "carryfn.h"
 #include "kernels.h"
 
 namespace pa {
 namespace {
-
-constexpr uint32_t kIdentity = 0xE4u;   // f(c) = c for c = 0..3
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
 {
@@ -40,18 +38,6 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
     return z ^ (z >> 31);
 }
 
-// Apply f then g.
-__device__ __forceinline__ uint32_t compose(uint32_t f, uint32_t g)
-{
-    uint32_t h = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-        h |= ((g >> (2 * ((f >> (2 * c)) & 3u))) & 3u) << (2 * c);
-    return h;
-}
-
-__device__ __forceinline__ uint32_t apply(uint32_t f, uint32_t c) { return (f >> (2 * c)) & 3u; }
-
 // Inclusive scan of one function per lane over a wavefront, in lane order.
 __device__ __forceinline__ uint32_t wave_scan(uint32_t f, int lane)
 {
@@ -59,17 +45,8 @@ __device__ __forceinline__ uint32_t wave_scan(uint32_t f, int lane)
     for (int d = 1; d < 64; d <<= 1) {
         const uint32_t prev = __shfl_up(f, d);
         if (lane >= d)
-            f = compose(prev, f);
+            f = carry_compose(prev, f);
     }
-    return f;
-}
-
-__device__ __forceinline__ uint32_t digit_function(uint64_t s)
-{
-    uint32_t f = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-        f |= (uint32_t)((s + (uint64_t)c) >> 32) << (2 * c);
     return f;
 }
 
@@ -308,10 +285,10 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
             }
         }
     }
-    uint32_t f = kIdentity;
+    uint32_t f = carry_fn_of_sum(s[0]);
 #pragma unroll
-    for (int i = 0; i < kPer; ++i)
-        f = compose(f, digit_function(s[i]));
+    for (int i = 1; i < kPer; ++i)
+        f = carry_compose(f, carry_fn_of_sum(s[i]));
 
     // inclusive scan of the thread functions in thread order: within each
     // wavefront by lane shuffles, then across the four wavefronts through LDS
@@ -321,13 +298,13 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     if (lane == 63)
         wtot[wave] = f;
     __syncthreads();
-    uint32_t before = kIdentity;              // the wavefronts before this one
+    uint32_t before = kCarryIdentity;              // the wavefronts before this one
     for (int w = 0; w < wave; ++w)
-        before = compose(before, wtot[w]);
+        before = carry_compose(before, wtot[w]);
 
     if (!kApply) {
         if (tid == kCarryThreads - 1)
-            a.desc[chunk] = compose(before, f);
+            a.desc[chunk] = carry_compose(before, f);
         return;
     }
     // carry entering this chunk: the functions of chunks 0 .. chunk-1 (written
@@ -339,25 +316,25 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
     {
         const uint32_t per_t = (chunk + kCarryThreads - 1) / kCarryThreads;
         const uint32_t lo = (uint32_t)tid * per_t;
-        uint32_t g = kIdentity;
+        uint32_t g = kCarryIdentity;
         for (uint32_t k = lo; k < lo + per_t && k < chunk; ++k)
-            g = compose(g, a.desc[k]);
+            g = carry_compose(g, a.desc[k]);
         g = wave_scan(g, lane);
         if (lane == 63)
             wpre[wave] = g;
         __syncthreads();
-        uint32_t all = kIdentity;
+        uint32_t all = kCarryIdentity;
 #pragma unroll
         for (int w = 0; w < kCarryThreads / 64; ++w)
-            all = compose(all, wpre[w]);
-        cin_chunk = apply(all, 0u);
+            all = carry_compose(all, wpre[w]);
+        cin_chunk = carry_apply(all, 0u);
     }
 
     // resolve this thread's digits; V digits of the chunk (and two past it) to LDS
     uint32_t excl = __shfl_up(f, 1);          // inclusive scan of the lane before
     if (lane == 0)
-        excl = kIdentity;
-    uint64_t carry = apply(compose(before, excl), cin_chunk);
+        excl = kCarryIdentity;
+    uint64_t carry = carry_apply(carry_compose(before, excl), cin_chunk);
     const uint32_t top = (uint32_t)(a.n & 31);
 #pragma unroll
     for (int i = 0; i < kPer + kExtra; ++i) {
