@@ -162,6 +162,24 @@ def test_largest_seven_prime_transform_closed_forms(pa, ctx):
         assert np.array_equal(got, top(v)), name
 
 
+def test_longest_five_prime_factor3_transform_closed_forms(pa, ctx):
+    """n = 350 000 000: 64-bit digits at L = 3 2^22 (96-bit digits would need
+    2^23, which the seven-prime layout cannot take); closed forms."""
+    n = 350_000_000
+    assert pa.pa_transform_length(n) == 3 << 22
+    m = n // 4 + 11
+    mask = (1 << n) - 1
+    sa, sb = 2468, 1357
+    c = _int(oracle.expand_operand(sa, n, True))
+    d = _int(oracle.expand_operand(sb, n, False))
+    top = lambda v: _words((v & mask) >> (n - m), m)
+    for name, x, v in [("one", 1, c + d), ("shift", 1 << (n - 5), (c << (n - 5)) + d),
+                       ("all_ones", mask, d - c)]:
+        _log(f"five-prime 3*2^22 key={name}")
+        got = pa.pa_hash(ctx, _words(x, n), sa, sb, n, m)
+        assert np.array_equal(got, top(v)), name
+
+
 def test_maximum_size_closed_forms(pa, ctx):
     """n = PA_MAX_N (transform length 2^25): closed forms that hold at any size."""
     n = pa.PA_MAX_N

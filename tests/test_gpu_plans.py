@@ -40,8 +40,13 @@ def _hash(pa, ctx, torch, d_key, b):
     return d_out.cpu().numpy().view(np.uint64).copy()
 
 
-# 2^k lengths (one and two passes) and 3 2^k lengths (two and three passes)
-CASES = [(40_000, 9_999), (1_000_003, 99_999), (3_200_000, 1_000_001), (10_000_000, 2_000_000)]
+# 2^k lengths (one and two passes) and a 3 2^k length (two and three passes,
+# the radix-3 step), in both digit layouts: 40 000 and 1 000 003 bits take
+# 64-bit digits (1024, 2^15); 3 200 000, 10 000 000 and 8 388 609 bits 96-bit
+# digits (2^17, 2^18, 3 2^16).  The 64-bit layout's only 3 2^k length, 3 2^22,
+# is covered below with closed forms.
+CASES = [(40_000, 9_999), (1_000_003, 99_999), (3_200_000, 1_000_001), (10_000_000, 2_000_000),
+         (8_388_609, 3_000_001)]
 
 
 @pytest.mark.parametrize("n,m", CASES)
@@ -60,6 +65,31 @@ def test_every_candidate_geometry_is_exact(pa, ctx, n, m):
             got = pa.pa_plan_get(ctx, n)
             assert (got["tile_log"], got["passes"]) == (c["tile_log"], c["passes"])
             assert np.array_equal(_hash(pa, ctx, torch, d_key, b), want), c
+    finally:
+        pa.pa_plan_set(ctx, n, None)
+
+
+def test_five_prime_factor3_geometries_closed_form(pa, ctx):
+    """n = 350 000 000 takes 64-bit digits at L = 3 2^22, the longest
+    factor-3 transform: every candidate geometry against the closed form of
+    the all-ones key, (c (2^n - 1) + d) mod 2^n = d - c."""
+    n, m = 350_000_000, 70_000_001
+    assert pa.pa_transform_length(n) == 3 << 22
+    mask = (1 << n) - 1
+    sa, sb = 97, 98
+    c = int.from_bytes(oracle.expand_operand(sa, n, True).astype("<u8").tobytes(), "little")
+    d = int.from_bytes(oracle.expand_operand(sb, n, False).astype("<u8").tobytes(), "little")
+    v = ((d - c) & mask) >> (n - m)
+    want = np.frombuffer(v.to_bytes(8 * workloads.words(m), "little"), dtype="<u8")
+    ones = np.full(workloads.words(n), np.uint64(0xFFFFFFFFFFFFFFFF), dtype=np.uint64)
+    cands = pa.pa_plan_candidates(n)[:12]
+    assert {c_["passes"] for c_ in cands} == {2, 3}
+    try:
+        for cand in cands:
+            _log(f"plan n={n} {cand}")
+            pa.pa_plan_set(ctx, n, cand)
+            got = pa.pa_hash(ctx, ones, sa, sb, n, m)
+            assert np.array_equal(got, want), cand
     finally:
         pa.pa_plan_set(ctx, n, None)
 
