@@ -231,8 +231,9 @@ __device__ __forceinline__ uint32_t root_pow(const Tables& tb, uint32_t E)
 __device__ __forceinline__ uint32_t swz(uint32_t e) { return e ^ (((e >> 8) & 15u) << 2); }
 
 // Radix-2^R DIF butterflies in registers: natural input, bit-reversed output,
-// with the constant powers of omega_64 of prime PI.
-template <int R, int PI>
+// with the constant powers of omega_64 of prime PI.  kHalfZero: the upper half
+// of the input is zero, so the first level is x[j + h] = x[j] w^j.
+template <int R, int PI, bool kHalfZero = false>
 __device__ __forceinline__ void dif_regs(uint32_t* x)
 {
     constexpr uint32_t p = PrimeConst<PI>::p;
@@ -246,6 +247,11 @@ __device__ __forceinline__ void dif_regs(uint32_t* x)
 #pragma unroll
             for (int j = 0; j < h; ++j) {
                 const uint32_t a = x[i0 + j], b = x[i0 + j + h];
+                if (kHalfZero && lh == R - 1) {
+                    const int e = j << (5 - lh);
+                    x[i0 + j + h] = j ? fmul_shoup(a, tw.w[e], tw.q[e], p) : a;
+                    continue;
+                }
                 x[i0 + j] = fadd(a, b, p);
                 if (j == 0) {
                     x[i0 + j + h] = fsub(a, b, p);
@@ -324,7 +330,11 @@ struct GlobalIO {
     uint32_t limit;
 };
 
-template <int R, bool kInv, int PI, int kIO = 0>
+// kHalf (the first register step of an operand's first pass, or the last one
+// of the final inverse pass, power-of-two rows): elements n >= 2^R / 2 of every
+// DFT are rows >= R / 2 of the pass, positions >= L / 2 >= D: zero on input
+// (forward: not read) or never stored (inverse: not written).
+template <int R, bool kInv, int PI, int kIO = 0, bool kHalf = false>
 __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, const Tables& tb,
                                          const GlobalIO& io = GlobalIO{nullptr, nullptr, 0u})
 {
@@ -354,9 +364,13 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
             b = root_pow<PI>(tb, step_exponent(g, o, c, kInv));
         if (!kInv) {
 #pragma unroll
-            for (int n = 0; n < RHO; ++n)
-                x[n] = (kIO == 1) ? io.in[base + n * nstep] : sm[sb ^ swz(n * nstep)];
-            dif_regs<R, PI>(x);
+            for (int n = 0; n < RHO; ++n) {
+                if (kHalf && n >= RHO / 2)
+                    x[n] = 0u;
+                else
+                    x[n] = (kIO == 1) ? io.in[base + n * nstep] : sm[sb ^ swz(n * nstep)];
+            }
+            dif_regs<R, PI, kHalf>(x);
             if (twiddle) {
                 uint32_t w = b;
 #pragma unroll
@@ -385,6 +399,8 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
             dit_regs<R, PI>(x);
 #pragma unroll
             for (int n = 0; n < RHO; ++n) {
+                if (kHalf && n >= RHO / 2)
+                    continue;
                 if (kIO == 2) {
                     if (base + n * nstep < io.limit) io.out[base + n * nstep] = x[n];
                 } else {
@@ -451,6 +467,18 @@ __device__ __forceinline__ void dispatch_step(int r, uint32_t* sm, int N, const 
     }
 }
 
+template <bool kInv, int PI>
+__device__ __forceinline__ void dispatch_step_half(int r, uint32_t* sm, int N, const StepGeo& g,
+                                                   const Tables& tb)
+{
+    switch (r) {
+    case 2: run_step<2, kInv, PI, 0, true>(sm, N, g, tb); break;
+    case 3: run_step<3, kInv, PI, 0, true>(sm, N, g, tb); break;
+    case 4: run_step<4, kInv, PI, 0, true>(sm, N, g, tb); break;
+    default: run_step<1, kInv, PI>(sm, N, g, tb); break;
+    }
+}
+
 // Geometry of step si of a pass (si counts the radix-3 step, if any, as 0).
 __device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int si, uint32_t col0)
 {
@@ -498,17 +526,19 @@ __device__ __forceinline__ void dispatch_step_io(int r, uint32_t* sm, int N, con
 // Steps first .. count-1 of the pass (forward), or their inverse count-1 .. first.
 template <bool kInv, int PI>
 __device__ __forceinline__ void run_pass_steps(const PassArgs& a, uint32_t* sm, int N, uint32_t col0,
-                                               int count, int first = 0)
+                                               int count, int first = 0, bool half = false)
 {
     const int has3 = a.f == 3;
     for (int k = first; k < count; ++k) {
         const int si = kInv ? count - 1 - (k - first) : k;
         const StepGeo g = step_geo(a, si, col0);
+        const int r = (int)((a.steps_code >> (4 * (si - has3))) & 15u);
         if (has3 && si == 0)
             run_step3<kInv, PI>(sm, N, g, a.tb);
+        else if (half && si == 0)
+            dispatch_step_half<kInv, PI>(r, sm, N, g, a.tb);
         else
-            dispatch_step<kInv, PI>((int)((a.steps_code >> (4 * (si - has3))) & 15u), sm, N, g,
-                                    a.tb);
+            dispatch_step<kInv, PI>(r, sm, N, g, a.tb);
         __syncthreads();
     }
 }
@@ -641,10 +671,23 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
     const GlobalIO io{data + blk0, data + blk0,
                       bv.store_limit > blk0 ? bv.store_limit - blk0 : 0u};
 
+    // An operand's first pass covers the whole array in one block of R rows;
+    // rows >= R / 2 are positions >= L / 2 >= D, all zero: they are neither
+    // loaded nor read by the first step.  The final inverse pass stores only
+    // positions below D, so its last step leaves rows >= R / 2 unwritten.
+    // (Power-of-two rows, a first or last step of radix >= 4; in the 96-bit
+    // layout's kernel only: the 64-bit one serves the short, latency-bound
+    // blocks, where the larger kernel measured slower than the saved work.)
+    const bool half_in = W == 3 && (bv.src == kSrcDigits || bv.src == kSrcSeed) && a.f == 1 &&
+                         r0 >= 2 && (a.mode != kFused || total >= 2);
+    const bool half_out = W == 3 && a.mode == kInverse && a.limit_to_digits && a.f == 1 && r0 >= 2;
+
     // Tile element (row, c) <-> global position blk0 + row S + col0 + c; moved
-    // in groups of 4 consecutive columns (C >= 4) or rows (C == 1).
+    // in groups of 4 consecutive columns (C >= 4) or rows (C == 1); quad u
+    // holds tile elements 4u .. 4u + 3.
     const int nq = N >> 2;
-    for (int u = threadIdx.x; u < nq && !hbm_in; u += blockDim.x) {
+    const int nq_in = half_in ? nq >> 1 : nq;
+    for (int u = threadIdx.x; u < nq_in && !hbm_in; u += blockDim.x) {
         uint32_t e, pos;
         if (logC >= 2) {
             const uint32_t row = (uint32_t)u >> (logC - 2);
@@ -686,7 +729,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
     __syncthreads();
 
     if (a.mode == kInverse) {
-        run_pass_steps<true, PI>(a, sm, N, col0, total);
+        run_pass_steps<true, PI>(a, sm, N, col0, total, 0, half_out);
     } else if (a.mode == kFused && hbm_in) {
         // as below, with the first forward step read from HBM and the last
         // inverse step (its inverse) written to HBM
@@ -703,7 +746,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
         // first inverse step together in registers, then the other inverse
         // steps.  The fused pass is the contiguous last pass (f = 1, no pass
         // twiddle), so its last step carries no twiddles.
-        run_pass_steps<false, PI>(a, sm, N, col0, total - 1);
+        run_pass_steps<false, PI>(a, sm, N, col0, total - 1, 0, half_in);
         const int rl = (int)((a.steps_code >> (4 * (a.nsteps - 1))) & 15u);
         dispatch_fused_middle<PI>(rl, sm, N, bv.other + (size_t)PI * a.L + blk0);
         __syncthreads();
@@ -711,7 +754,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
     } else if (a.f == 1 && logC == 0 && a.nsteps >= 2 && ((a.steps_code >> (4 * (a.nsteps - 1))) & 15u) >= 2) {
         // forward contiguous pass: all steps but the last through LDS, the
         // last straight to HBM
-        run_pass_steps<false, PI>(a, sm, N, col0, total - 1, hbm_in ? 1 : 0);
+        run_pass_steps<false, PI>(a, sm, N, col0, total - 1, hbm_in ? 1 : 0, half_in);
         const int rl = (int)((a.steps_code >> (4 * (a.nsteps - 1))) & 15u);
         const uint32_t lim = bv.store_limit > blk0 ? bv.store_limit - blk0 : 0u;
         const uint32_t sw = a.scale_w[PI], sq = a.scale_q[PI];
@@ -723,10 +766,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm)
             last_step_store<4, PI>(sm, N, data + blk0, lim, a.scale != 0, sw, sq);
         return;
     } else {
-        run_pass_steps<false, PI>(a, sm, N, col0, total, hbm_in ? 1 : 0);
+        run_pass_steps<false, PI>(a, sm, N, col0, total, hbm_in ? 1 : 0, half_in);
     }
 
-    for (int u = threadIdx.x; u < nq; u += blockDim.x) {
+    for (int u = threadIdx.x; u < (half_out ? nq >> 1 : nq); u += blockDim.x) {
         uint32_t e, pos;
         if (logC >= 2) {
             const uint32_t row = (uint32_t)u >> (logC - 2);
