@@ -85,3 +85,17 @@ def test_single_hip_runtime_in_process():
     with open("/proc/self/maps") as f:
         paths = {line.split()[-1] for line in f if "libamdhip64" in line}
     assert len(paths) == 1, paths
+
+
+def test_build_scripts_load_before_the_libraries_exist():
+    """build() must work on a fresh checkout: its build scripts load by file
+    path, without importing the packages (which refuse to load before their
+    libraries exist)."""
+    import subprocess
+    import sys
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "..")
+    code = ("import sys, __graft_entry__ as g, os; "
+            "g._load_script(os.path.join(g.ROOT, 'paper_1910_04429_amd', 'build.py'), 'a'); "
+            "g._load_script(os.path.join(g.ROOT, 'oracle', 'build.py'), 'b'); "
+            "assert 'paper_1910_04429_amd' not in sys.modules and 'oracle' not in sys.modules")
+    subprocess.run([sys.executable, "-c", code], cwd=root, check=True)
