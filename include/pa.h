@@ -133,11 +133,14 @@ int pa_hash_profile(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_
  * does not say whether g may be reused across blocks (Section 2.2 has it
  * chosen at random and publicly); reuse is the caller's security decision.
  *   pa_mul_create: transform c (expanded from seed_a, or the device words d_c,
- *     which must be odd) for blocks of n bits, queued on `stream`.
+ *     which must be odd) for blocks of n bits, queued on `stream`.  With d_c
+ *     it first reads c's low word in `stream` order and waits for it.
  *   pa_hash_mul_async: hash the device key d_key (ceil(n/64) words) with that
  *     c and the addend of seed_b; m output bits into d_out.  Same ordering
- *     rules as pa_hash_async (the context's workspace is reused).
- *   pa_mul_destroy: waits for the device, then frees the spectrum.
+ *     rules as pa_hash_async (the context's workspace is reused).  ctx may be
+ *     any context on the device the multiplier was made on (else PA_EINVAL).
+ *   pa_mul_destroy: waits for the device, then frees the spectrum; it may
+ *     come before or after pa_destroy of the creating context.
  */
 typedef struct pa_mul pa_mul;
 int pa_mul_create(pa_ctx *ctx, uint64_t seed_a, const uint64_t *d_c, uint64_t n, void *stream,
@@ -173,7 +176,10 @@ typedef struct pa_batch pa_batch;
  * blocks; see pa_batch_bytes) and upload its job table.  Invalid blocks get
  * their status and are skipped; the call fails only if nothing can run (or on
  * allocation / device errors).  The batch keeps the pointers of `jobs`, not
- * the array itself; the buffers they point to must outlive the batch.
+ * the array itself; the buffers they point to must outlive the batch.  The
+ * low word of each explicit c is read here with a synchronous copy, so c must
+ * already be written.  Runs and captures need `ctx`; pa_batch_destroy does
+ * not, and may follow pa_destroy(ctx).
  */
 int pa_batch_create(pa_ctx *ctx, pa_job *jobs, size_t count, pa_batch **batch);
 
@@ -236,19 +242,24 @@ int pa_server_create(int device, const pa_server_opts *opts, pa_server **server)
 int pa_server_submit(pa_server *s, const uint64_t *key, uint64_t seed_a, uint64_t seed_b,
                      uint64_t n, uint64_t m, uint64_t *out, int flags, uint64_t *ticket);
 
-/* Block until the request is done; its status and submit-to-result latency. */
+/* Block until the request is done; its status and submit-to-result latency.
+ * The ticket is then retired: a second wait on it returns PA_EINVAL.  Tickets
+ * never waited on are kept until pa_server_destroy. */
 int pa_server_wait(pa_server *s, uint64_t ticket, int *status, double *latency_ms);
 
 /* Block until every request submitted so far is done. */
 int pa_server_drain(pa_server *s);
 
+/* Counts and latency percentiles over every request completed so far (the
+ * server keeps one latency per completed request for them). */
 int pa_server_get_stats(pa_server *s, pa_server_stats *stats);
 
 /*
- * Open-loop load: submit jobs[i] (key/out/seeds/n/m; c and d must be NULL) at
- * arrival_s[i] seconds after the call starts, from the calling thread, then
- * wait for all.  latency_ms[i] and status[i] (either may be NULL) receive each
- * request's submit-to-result latency and status.
+ * Open-loop load: submit jobs[i] (key/out/seeds/n/m) at arrival_s[i] seconds
+ * after the call starts, from the calling thread, then wait for all.
+ * latency_ms[i] and status[i] (either may be NULL) receive each request's
+ * submit-to-result latency (-1 if it was not submitted) and status; a job
+ * with c or d set is not submitted and gets PA_EINVAL.
  */
 int pa_server_run_trace(pa_server *s, const pa_job *jobs, const double *arrival_s, size_t count,
                         int flags, double *latency_ms, int *status);

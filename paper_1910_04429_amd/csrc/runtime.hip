@@ -625,6 +625,7 @@ int set_error(pa_ctx* ctx, int code, const char* what) { return fail(ctx, code, 
 
 struct pa_batch {
     pa_ctx* ctx = nullptr;
+    int device = 0;      // for pa_batch_destroy, which may follow pa_destroy(ctx)
     struct Group {
         Plan plan;
         uint32_t first = 0, count = 0;   // range in the job table
@@ -1084,7 +1085,7 @@ int pa_hash_ex(pa_ctx* ctx, const uint64_t* key, const uint64_t* c, const uint64
 }
 
 struct pa_mul {
-    pa_ctx* ctx;
+    int device;       // where A lives; the creating context may be destroyed first
     uint64_t n;
     uint32_t* A;      // c-hat for blocks of n bits, scaled by 2^32 / L
     Plan plan;        // the geometry c-hat was made with (its spectrum order)
@@ -1099,15 +1100,17 @@ int pa_mul_create(pa_ctx* ctx, uint64_t seed_a, const uint64_t* d_c, uint64_t n,
     *out = nullptr;
     PA_HIP(ctx, hipSetDevice(ctx->device));
     if (d_c) {
+        // read c's low word in the caller's stream order, after whatever wrote it
         uint64_t w0 = 0;
-        PA_HIP(ctx, hipMemcpy(&w0, d_c, 8, hipMemcpyDeviceToHost));
+        PA_HIP(ctx, hipMemcpyAsync(&w0, d_c, 8, hipMemcpyDeviceToHost, (hipStream_t)stream));
+        PA_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
         if ((w0 & 1) == 0) return fail(ctx, PA_EINVAL, "multiplier c must be odd");
     }
     Plan pl;
     if (!plan_for(ctx, plan_len(n), &pl)) return fail(ctx, PA_EINVAL, "internal: bad pass plan");
     pa_mul* mh = new (std::nothrow) pa_mul;
     if (!mh) return PA_ENOMEM;
-    mh->ctx = ctx;
+    mh->device = ctx->device;
     mh->n = n;
     mh->A = nullptr;
     mh->plan = pl;
@@ -1143,6 +1146,8 @@ int pa_hash_mul_async(pa_ctx* ctx, const pa_mul* mh, const uint64_t* d_key, uint
     int rc = check_sizes(ctx, mh->n, m);
     if (rc) return rc;
     if (!d_key || !d_out) return fail(ctx, PA_EINVAL, "null key or output pointer");
+    if (mh->device != ctx->device)
+        return fail(ctx, PA_EINVAL, "multiplier was made on another device");
     PA_HIP(ctx, hipSetDevice(ctx->device));
     rc = ensure_workspace(ctx, mh->n);
     if (rc) return rc;
@@ -1170,7 +1175,7 @@ int pa_hash_mul_async(pa_ctx* ctx, const pa_mul* mh, const uint64_t* d_key, uint
 void pa_mul_destroy(pa_mul* mh)
 {
     if (!mh) return;
-    (void)hipSetDevice(mh->ctx->device);
+    (void)hipSetDevice(mh->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(mh->A);
     delete mh;
@@ -1179,7 +1184,7 @@ void pa_mul_destroy(pa_mul* mh)
 void pa_batch_destroy(pa_batch* b)
 {
     if (!b) return;
-    (void)hipSetDevice(b->ctx->device);
+    (void)hipSetDevice(b->device);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     (void)hipFree(b->d_jobs);
@@ -1222,6 +1227,7 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
     pa_batch* b = new (std::nothrow) pa_batch;
     if (!b) return PA_ENOMEM;
     b->ctx = ctx;
+    b->device = ctx->device;
     b->valid = ok.size();
     // groups and workspace layout
     std::vector<JobDesc> h(ok.size());

@@ -69,7 +69,9 @@ struct pa_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request*> pending;
-    std::map<uint64_t, Request*> all;
+    std::map<uint64_t, Request*> all;   // submitted and not yet waited on
+    uint64_t outstanding = 0;           // submitted and not yet done
+    std::vector<double> lat_ok;         // latency of every completed request
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread worker;
@@ -136,9 +138,11 @@ void finish(pa_server* s, Slot& sl, int status)
     r->finished = Clock::now();
     r->status = status;
     r->done = true;
+    --s->outstanding;
     if (status == PA_OK) {
         ++s->completed;
         s->bits += r->n;
+        s->lat_ok.push_back(ms_between(r->submitted, r->finished));
     } else {
         ++s->failed;
     }
@@ -267,6 +271,10 @@ int pa_server_create(int device, const pa_server_opts* opts, pa_server** out)
         return PA_ENOMEM;
     }
     s->arena = new (std::nothrow) pa::Arena(opts->hbm_budget);
+    if (!s->arena) {
+        pa_server_destroy(s);
+        return PA_ENOMEM;
+    }
     s->slots.resize(opts->slots);
     for (auto& sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -305,6 +313,7 @@ int pa_server_submit(pa_server* s, const uint64_t* key, uint64_t seed_a, uint64_
             s->any = true;
         }
         s->all[r->ticket] = r;
+        ++s->outstanding;
         s->pending.push_back(r);
     }
     s->cv_work.notify_one();
@@ -322,6 +331,9 @@ int pa_server_wait(pa_server* s, uint64_t ticket, int* status, double* latency_m
     s->cv_done.wait(lk, [&] { return r->done; });
     if (status) *status = r->status;
     if (latency_ms) *latency_ms = ms_between(r->submitted, r->finished);
+    // done: the scheduler no longer holds r (finish() let go of it under the lock)
+    s->all.erase(it);
+    delete r;
     return PA_OK;
 }
 
@@ -329,11 +341,7 @@ int pa_server_drain(pa_server* s)
 {
     if (!s) return PA_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_done.wait(lk, [&] {
-        for (auto& kv : s->all)
-            if (!kv.second->done) return false;
-        return true;
-    });
+    s->cv_done.wait(lk, [&] { return s->outstanding == 0; });
     return PA_OK;
 }
 
@@ -347,10 +355,7 @@ int pa_server_get_stats(pa_server* s, pa_server_stats* st)
     st->bits = s->bits;
     st->peak_inflight = s->admitted_peak;
     st->peak_bytes = s->arena ? s->arena->peak() : 0;
-    std::vector<double> lat;
-    for (auto& kv : s->all)
-        if (kv.second->done && kv.second->status == PA_OK)
-            lat.push_back(ms_between(kv.second->submitted, kv.second->finished));
+    std::vector<double> lat = s->lat_ok;
     if (!lat.empty()) {
         std::sort(lat.begin(), lat.end());
         auto pct = [&](double q) {
@@ -382,8 +387,10 @@ int pa_server_run_trace(pa_server* s, const pa_job* jobs, const double* arrival_
             if (left > std::chrono::microseconds(200))
                 std::this_thread::sleep_for(left - std::chrono::microseconds(100));
         }
-        rcs[i] = pa_server_submit(s, jobs[i].key, jobs[i].seed_a, jobs[i].seed_b, jobs[i].n,
-                                  jobs[i].m, jobs[i].out, flags, &tickets[i]);
+        rcs[i] = (jobs[i].c || jobs[i].d)
+                     ? PA_EINVAL
+                     : pa_server_submit(s, jobs[i].key, jobs[i].seed_a, jobs[i].seed_b, jobs[i].n,
+                                        jobs[i].m, jobs[i].out, flags, &tickets[i]);
     }
     for (size_t i = 0; i < count; ++i) {
         int st = rcs[i];

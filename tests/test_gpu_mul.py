@@ -65,3 +65,26 @@ def test_explicit_multiplier(pa, ctx):
     with pytest.raises(pa.PAError) as e:
         pa.pa_mul_create(ctx, 0, n, c=even)
     assert e.value.status == pa.PA_EINVAL
+
+
+def test_multiplier_outlives_its_context_and_serves_another(pa):
+    """A multiplier made on one context hashes through a second context on
+    the same device, and is freed after its creating context is gone."""
+    import torch
+    n, m = 200_003, 60_000
+    rng = np.random.default_rng(8)
+    key = rng.integers(0, 2**64, workloads.words(n), dtype=np.uint64)
+    d_key = torch.from_numpy(key.view(np.int64)).cuda()
+    d_out = torch.zeros(workloads.words(m), dtype=torch.int64, device="cuda")
+    first = pa.pa_init(0)
+    mul = pa.pa_mul_create(first, 41, n)
+    torch.cuda.synchronize()
+    pa.pa_destroy(first)
+    second = pa.pa_init(0)
+    try:
+        pa.pa_hash_mul_async(second, mul, d_key, 42, n, m, d_out)
+        torch.cuda.synchronize()
+    finally:
+        pa.pa_mul_destroy(mul)
+        pa.pa_destroy(second)
+    assert np.array_equal(d_out.cpu().numpy().view(np.uint64), oracle.pa_hash(key, 41, 42, n, m))

@@ -134,3 +134,25 @@ def test_served_workload_full_sizes(pa):
         _log(f"oracle check n={b.n}")
         assert np.array_equal(_host(jobs[i]["out"]),
                               oracle.pa_hash(b.key(), b.seed_a, b.seed_b, b.n, b.m))
+
+
+def test_waited_ticket_is_retired_and_explicit_operands_are_refused(pa):
+    import torch
+    blocks, _ = workloads.served_requests(24, 3, n_lo=1e3, n_hi=1e5)
+    jobs = _jobs(blocks)
+    with pa.Server(hbm_budget=64 << 20, slots=2, max_n=100_000) as srv:
+        j, b = jobs[0], blocks[0]
+        t = srv.submit(j["key"], b.seed_a, b.seed_b, b.n, b.m, j["out"])
+        assert srv.wait(t)[0] == pa.PA_OK
+        with pytest.raises(pa.PAError) as e:
+            srv.wait(t)
+        assert e.value.status == pa.PA_EINVAL
+        # a trace job with an explicit operand is not submitted
+        jobs[1]["c"] = torch.ones(workloads.words(blocks[1].n), dtype=torch.int64, device="cuda")
+        lat, st = srv.run_trace(jobs[1:], [0.0, 0.0])
+        assert st == [pa.PA_EINVAL, pa.PA_OK] and lat[0] == -1 and lat[1] >= 0
+        srv.drain()
+        stats = srv.stats()
+    assert stats["completed"] == 2 and stats["failed"] == 0
+    for b, j in zip(blocks[::2], jobs[::2]):
+        assert np.array_equal(_host(j["out"]), oracle.pa_hash(b.key(), b.seed_a, b.seed_b, b.n, b.m))
