@@ -389,8 +389,8 @@ def served(pa, torch, workloads, count):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build "
-              "has no multi-GPU path", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library "
+              "hashes each block on one GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     if args.ingest_counters:
