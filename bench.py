@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="n1e8", choices=["n1e6", "n1e7", "n1e8"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-single-thread", action="store_true",
+                    help="also time the oracle on one thread (about 25 s at n = 10^8)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the n=1e6, batched and served measurements")
     ap.add_argument("--profile-runs", type=int, default=5)
@@ -180,16 +182,24 @@ def ingest_counters(dirs, calib_mib, path=COUNTERS):
     return out
 
 
-def cpu_baseline(blk, key):
+def cpu_baseline(blk, key, single_thread=False):
     import oracle
     cores = 9   # the oracle splits two Karatsuba levels onto 3 x 3 threads
     t0 = time.perf_counter()
     y = oracle.pa_hash(key, blk.seed_a, blk.seed_b, blk.n, blk.m, par_levels=2)
     dt = time.perf_counter() - t0
-    return y, {"value": blk.n / dt / 1e6, "unit": "Mbps", "cores": cores, "kind": "oracle",
-               "sample": f"one full block n={blk.n} m={blk.m} ({dt:.2f} s), "
-                         f"Karatsuba low product on {cores} threads; host has "
-                         f"{os.cpu_count()} logical CPUs"}
+    res = {"value": blk.n / dt / 1e6, "unit": "Mbps", "cores": cores, "kind": "oracle",
+           "sample": f"one full block n={blk.n} m={blk.m} ({dt:.2f} s), "
+                     f"Karatsuba low product on {cores} threads; host has "
+                     f"{os.cpu_count()} logical CPUs"}
+    if single_thread:
+        t0 = time.perf_counter()
+        y1 = oracle.pa_hash(key, blk.seed_a, blk.seed_b, blk.n, blk.m, par_levels=0)
+        dt1 = time.perf_counter() - t0
+        assert np.array_equal(y1, y), "the oracle's threaded and single-thread results differ"
+        res["single_thread"] = {"value": blk.n / dt1 / 1e6, "unit": "Mbps", "cores": 1,
+                                "sample": f"the same block on one thread ({dt1:.2f} s)"}
+    return y, res
 
 
 def time_single(pa, ctx, torch, blk, steps, warmup, plan=None):
@@ -474,7 +484,7 @@ def main():
     cpu = None
     bit_exact = None
     if not args.no_cpu:
-        want, cpu = cpu_baseline(blk, key)
+        want, cpu = cpu_baseline(blk, key, args.cpu_single_thread)
         bit_exact = bool(np.array_equal(gpu_out, want))
 
     plan = pa.pa_plan_get(ctx, blk.n)
