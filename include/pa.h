@@ -62,7 +62,9 @@ typedef struct pa_ctx pa_ctx;
 /* Create a context on HIP device `device` (its own stream and tables). */
 int pa_init(pa_ctx **ctx, int device);
 
-/* Release the context and everything it owns.  NULL is allowed. */
+/* Wait for the device (work queued on any stream, including callers' streams
+ * through the _async calls), then release the context and everything it owns.
+ * NULL is allowed. */
 void pa_destroy(pa_ctx *ctx);
 
 /* Static text for a status code. */

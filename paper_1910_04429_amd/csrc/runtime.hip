@@ -977,7 +977,9 @@ void pa_destroy(pa_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    // work queued on callers' streams (pa_hash_async and the like) may still
+    // use the workspace and tables: wait for the whole device, not just ctx->stream
+    (void)hipDeviceSynchronize();
     free_workspace(ctx);
     (void)hipFree(ctx->d_key);
     (void)hipFree(ctx->d_out);
