@@ -237,6 +237,7 @@ int ensure_staging(pa_ctx* ctx, uint64_t words, bool operands)
     if (words <= ctx->cap_words && (!operands || ctx->d_c))
         return PA_OK;
     const uint64_t w = words > ctx->cap_words ? words : ctx->cap_words;
+    if (ctx->cap_words) PA_HIP(ctx, hipDeviceSynchronize());   // nothing may still use them
     (void)hipFree(ctx->d_key);
     (void)hipFree(ctx->d_out);
     (void)hipFree(ctx->d_c);
