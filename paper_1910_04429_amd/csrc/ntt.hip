@@ -34,6 +34,7 @@
 // both operands share the same scrambled spectrum, which the pointwise product
 // does not care about.
 #include "kernels.h"
+#include "swizzle.h"
 
 namespace pa {
 namespace {
@@ -222,18 +223,6 @@ __device__ __forceinline__ uint32_t root_pow(const Tables& tb, uint32_t E)
     const uint32_t hi = tb.pass_hi[PI * kRootHi + (E >> 12)];
     return fmul_mont(lo, hi, PrimeConst<PI>::p, PrimeConst<PI>::pneg);
 }
-
-// LDS index of tile element e: XOR of bits 2..5 with bits 6..9.  It only
-// permutes the 16 aligned 4-element groups of each 64-element block (by one
-// value per block), so it maps every tile, 2^k or 3 2^k elements, onto
-// itself, keeps 4-element groups together for the 16-byte tile loads and
-// stores, and spreads the step accesses over the banks: a wave's lanes
-// differ in bits 4..9 in the radix-16 step of stride 16 and in the unit-stride
-// steps of the strided tiles, and bits 6..9 land on bank bits 2..5.  It is
-// linear over GF(2): the elements of one small DFT sit at base + n nstep with
-// base and n nstep on disjoint bits, so their indices are
-// swz(base) ^ swz(n nstep), one vector XOR with a wave-uniform term.
-__device__ __forceinline__ uint32_t swz(uint32_t e) { return e ^ (((e >> 6) & 15u) << 2); }
 
 // Radix-2^R DIF butterflies in registers: natural input, bit-reversed output,
 // with the constant powers of omega_64 of prime PI.  kHalfZero: the upper half
