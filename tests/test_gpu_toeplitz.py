@@ -1,9 +1,9 @@
 """GPU tests of the Toeplitz-hash variant (pa_toeplitz, pa_toeplitz_async).
 
-Bit-exact against the Toeplitz oracle: whole outputs at small and n = 10^6
-sizes; at n = 10^7 and n = 10^8 (two key pieces) sampled output bits plus
-properties that check every output bit (unit-vector keys select a window of
-t; GF(2) linearity in the key).
+Bit-exact against the Toeplitz oracle: whole outputs at small, n = 10^6 and
+n = 10^7 sizes; at n = 10^7 and n = 10^8 (two key pieces) also sampled output
+bits plus properties that check every output bit (unit-vector keys select a
+window of t; GF(2) linearity in the key).
 """
 import sys
 
@@ -107,6 +107,24 @@ def test_device_entry_point_n1e6(pa, ctx):
     pa.pa_toeplitz_async(ctx, d_key, d_t, 0, blk.n, blk.m, d_out)
     torch.cuda.synchronize()
     assert np.array_equal(d_out.cpu().numpy().view(np.uint64), got)
+
+
+@pytest.mark.timeout(400)
+def test_full_output_n1e7(pa, ctx):
+    """The whole n = 10^7, m = 2 10^6 output against the oracle (one window
+    parity per output bit, spread over every host thread)."""
+    import os
+    import time
+    import torch
+    blk = workloads.single("n1e7")
+    key = blk.key()
+    y = _run(pa, ctx, torch, key, blk.seed_a, blk.n, blk.m)
+    threads = min(16, os.cpu_count() or 1)   # the host share of one GPU
+    _log(f"toeplitz n1e7 full output: oracle on {threads} threads")
+    t0 = time.perf_counter()
+    want = oracle.toeplitz(key, blk.seed_a, blk.n, blk.m, threads=threads)
+    _log(f"toeplitz n1e7 full output: oracle took {time.perf_counter() - t0:.1f} s")
+    assert np.array_equal(y, want)
 
 
 def _run(pa, ctx, torch, key, seed, n, m):
