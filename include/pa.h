@@ -102,6 +102,28 @@ int pa_hash_async(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_t 
                   uint64_t n, uint64_t m, uint64_t *d_out, void *stream);
 
 /*
+ * Allocation-free variant of pa_hash_async, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, result and stream ordering as
+ * pa_hash_async, and the same kernels; the block's two spectra and carry state
+ * live in a fixed scratch area of PA_NOALLOC_MAX_BYTES on each GPU instead of
+ * the context's workspace.  That area is set aside when the library's code is
+ * loaded on a GPU and held until the process ends; pa_init takes its address.
+ * The call allocates and frees nothing and never synchronises.
+ *   Limit: a block needs its spectra and carry state (pa_workspace_bytes(n),
+ *   plus at most 768 bytes of alignment) to fit; every n up to 3 * 2^25 =
+ *   100 663 296 bits does (the paper's largest block, 10^8 bits, included).
+ *   Larger n returns PA_EINVAL with the sizes in pa_last_error.
+ *   Sharing: every call on one GPU, from any context or thread, uses that
+ *   GPU's one scratch area, which keeps the last call's contents (nothing in
+ *   it needs to start at zero).  Calls that overlap on one GPU race and give
+ *   wrong results: order them on one stream or synchronise between them.
+ */
+#define PA_NOALLOC_MAX_BYTES ((uint64_t)120 << 20)
+int pa_hash_async_noalloc(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, uint64_t seed_b,
+                          uint64_t n, uint64_t m, uint64_t *d_out, void *stream);
+
+/*
  * Per-launch timing of one pa_hash_async call, for measurement.  The same
  * kernels run as in pa_hash_async on `stream`; each launch carries a start and
  * stop event stamped by its own dispatch (hipExtLaunchKernelGGL, so nothing

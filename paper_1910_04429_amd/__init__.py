@@ -32,6 +32,7 @@ PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENODEV = 0, 1, 2, 3, 4
 PA_MAX_N = 1 << 29
 PA_TOEPLITZ_MAX_M = 3 << 24
 PA_PROFILE_MAX = 32
+PA_NOALLOC_MAX_BYTES = 120 << 20
 KERNEL_KINDS = {0: "ntt_pass", 1: "carry_local", 2: "carry_scan (reserved)", 3: "carry_apply"}
 
 
@@ -99,6 +100,9 @@ _lib.pa_hash_ex.argtypes = [ctypes.c_void_p, _u64p, _u64p, _u64p, _u64, _u64, _u
 _lib.pa_hash_async.restype = ctypes.c_int
 _lib.pa_hash_async.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _u64, _u64, _u64, _u64,
                                ctypes.c_void_p, ctypes.c_void_p]
+_lib.pa_hash_async_noalloc.restype = ctypes.c_int
+_lib.pa_hash_async_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _u64, _u64, _u64, _u64,
+                                       ctypes.c_void_p, ctypes.c_void_p]
 _lib.pa_hash_profile.restype = ctypes.c_int
 _lib.pa_hash_profile.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _u64, _u64, _u64, _u64,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Profile)]
@@ -254,6 +258,16 @@ def pa_hash_async(ctx, d_key, seed_a: int, seed_b: int, n: int, m: int, d_out,
     _check(ctx, _lib.pa_hash_async(ctx, _dev_ptr(d_key, words(n), "d_key"), seed_a & MASK64,
                                    seed_b & MASK64, n, m, _dev_ptr(d_out, words(m), "d_out"),
                                    _stream_handle(stream)))
+
+
+def pa_hash_async_noalloc(ctx, d_key, seed_a: int, seed_b: int, n: int, m: int, d_out,
+                          stream=None) -> None:
+    """pa_hash_async without any device allocation: the block's working memory
+    is the library's fixed per-GPU scratch (calls overlapping on one GPU race)."""
+    _check(ctx, _lib.pa_hash_async_noalloc(ctx, _dev_ptr(d_key, words(n), "d_key"),
+                                           seed_a & MASK64, seed_b & MASK64, n, m,
+                                           _dev_ptr(d_out, words(m), "d_out"),
+                                           _stream_handle(stream)))
 
 
 def pa_hash_profile(ctx, d_key, seed_a: int, seed_b: int, n: int, m: int, d_out,

@@ -16,6 +16,9 @@ struct pa_ctx {
     uint32_t* A = nullptr;            // c-hat   [primes][L]
     uint32_t* B = nullptr;            // x-hat, then the product residues [primes][L]
     uint32_t* status = nullptr;       // carry state: the carry function of each chunk
+    // device address of this GPU's copy of the allocation-free entry point's
+    // scratch (taken with hipGetSymbolAddress in pa_init)
+    uint8_t* scratch = nullptr;
     // staging for the synchronous (host memory) entry points
     uint64_t cap_words = 0;
     uint64_t* d_key = nullptr;

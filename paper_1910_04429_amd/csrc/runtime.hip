@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -624,6 +625,41 @@ int set_error(pa_ctx* ctx, int code, const char* what) { return fail(ctx, code, 
 
 }  // namespace pa
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point (pa_hash_async_noalloc): the two
+// spectra and the carry state of one block, in device memory that exists from
+// the moment the library's code object is loaded on a GPU until the process
+// ends.  In host code `scratch` is only a stand-in for the symbol, never a
+// device address: each GPU holds its own copy, whose address hipGetSymbolAddress
+// gives once per device (scratch_address, from pa_init), and only that address
+// is ever passed to a kernel.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[PA_NOALLOC_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {};
+
+// The device address of `device`'s copy of the scratch; that device must be
+// current.  Taken on the first call for a device and kept.
+int scratch_address(pa_ctx* ctx, int device, uint8_t** out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(ctx, PA_ENODEV, "device index too large");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(ctx, PA_EDEVICE, "hipGetSymbolAddress(scratch)", e);
+        g_scratch[device] = static_cast<uint8_t*>(p);
+    }
+    *out = g_scratch[device];
+    return PA_OK;
+}
+
+}  // namespace
+
 struct pa_batch {
     pa_ctx* ctx = nullptr;
     int device = 0;      // for pa_batch_destroy, which may follow pa_destroy(ctx)
@@ -963,6 +999,7 @@ int pa_init(pa_ctx** out, int device)
             rc = PA_EDEVICE;
             break;
         }
+        rc = scratch_address(ctx, device, &ctx->scratch);
     } while (0);
     delete[] h_lo;
     delete[] h_hi;
@@ -1017,6 +1054,38 @@ int pa_hash_async(pa_ctx* ctx, const uint64_t* d_key, uint64_t seed_a, uint64_t 
     PA_HIP(ctx, hipSetDevice(ctx->device));
     return enqueue(ctx, d_key, nullptr, nullptr, seed_a, seed_b, n, m, d_out,
                    (hipStream_t)stream);
+}
+
+int pa_hash_async_noalloc(pa_ctx* ctx, const uint64_t* d_key, uint64_t seed_a, uint64_t seed_b,
+                          uint64_t n, uint64_t m, uint64_t* d_out, void* stream)
+{
+    int rc = check_sizes(ctx, n, m);
+    if (rc) return rc;
+    if (!d_key || !d_out) return fail(ctx, PA_EINVAL, "null key or output pointer");
+    const uint64_t need = block_workspace_bytes(n);
+    if (need > PA_NOALLOC_MAX_BYTES) {
+        char what[160];
+        snprintf(what, sizeof what,
+                 "n = %llu needs %llu scratch bytes; the allocation-free entry point has "
+                 "PA_NOALLOC_MAX_BYTES = %llu",
+                 (unsigned long long)n, (unsigned long long)need,
+                 (unsigned long long)PA_NOALLOC_MAX_BYTES);
+        return fail(ctx, PA_EINVAL, what);
+    }
+    if (!ctx->scratch) return fail(ctx, PA_EDEVICE, "scratch address missing");
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    // Nothing in the scratch must start at zero: the first forward pass writes
+    // every residue of both spectra, and the carry kernels' first launch writes
+    // every chunk's carry function before the second reads any.
+    BlockBufs b;
+    block_layout(n, ctx->scratch, &b);
+    b.key = reinterpret_cast<const uint32_t*>(d_key);
+    b.seed_a = seed_a;
+    b.seed_b = seed_b;
+    b.n = n;
+    b.m = m;
+    b.out = d_out;
+    return enqueue_block(ctx, b, (hipStream_t)stream);
 }
 
 int pa_hash_profile(pa_ctx* ctx, const uint64_t* d_key, uint64_t seed_a, uint64_t seed_b,

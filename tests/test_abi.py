@@ -48,6 +48,17 @@ def test_host_helpers():
     assert pa.pa_strerror(pa.PA_EINVAL) == "invalid argument"
 
 
+def test_noalloc_scratch_holds_every_block_up_to_3_2_25_bits():
+    """The allocation-free entry point's scratch covers the spectra and carry
+    state (plus at most 768 bytes of alignment) of every block of at most
+    3 * 2^25 bits, the paper's largest block of 10^8 bits included."""
+    import paper_1910_04429_amd as pa
+    top = 3 << 25
+    worst = max(pa.pa_workspace_bytes(n) for n in list(range(64, top, 6144)) + [10**8, top])
+    assert worst + 768 <= pa.PA_NOALLOC_MAX_BYTES
+    assert pa.pa_workspace_bytes(top + 1) + 768 > pa.PA_NOALLOC_MAX_BYTES
+
+
 def test_null_context_is_rejected():
     lib = ctypes.CDLL(LIB)
     lib.pa_hash.restype = ctypes.c_int
