@@ -40,6 +40,8 @@ def parse():
                     help="also time the oracle on one thread (about 25 s at n = 10^8)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the n=1e6, batched and served measurements")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="with --no-cpu: time only the 256-block batch (quick check)")
     ap.add_argument("--profile-runs", type=int, default=5)
     ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--plan", default=None, metavar="T,TS,R0",
@@ -315,29 +317,38 @@ def cached_multiplier(pa, ctx, torch, blk, d_key):
 
 
 def batched_vs_plain(pa, ctx, torch, workloads):
-    """256 blocks, n log-uniform in [1e5, 1e7]: one captured batch vs the same
-    blocks hashed one at a time."""
+    """256 blocks, n log-uniform in [1e5, 1e7]: the grouped launches (captured
+    into a HIP graph and replayed) against the same blocks hashed one at a time."""
     blocks = workloads.batch_blocks(3, 256)
     bits = sum(b.n for b in blocks)
     jobs = [{"key": torch.from_numpy(b.key().view(np.int64)).cuda(),
              "out": torch.zeros(workloads.words(b.m), dtype=torch.int64, device="cuda"),
              "n": b.n, "m": b.m, "seed_a": b.seed_a, "seed_b": b.seed_b} for b in blocks]
-    batch = pa.Batch(ctx, jobs)
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    try:
-        batch.capture()
-        for _ in range(3):
-            batch.run()
-        torch.cuda.synchronize()
-        s.record()
-        reps = 10
-        for _ in range(reps):
-            batch.run()
-        e.record()
-        torch.cuda.synchronize()
-        ms_batch = s.elapsed_time(e) / reps
-    finally:
-        batch.close()
+    res = {"workload": "256 blocks, n log-uniform in [1e5, 1e7], m = round(r n), "
+                       "r uniform in [0.05, 0.5], seed 3", "bits": bits}
+    for name, mode in (("grouped", pa.PA_BATCH_GROUPED),):
+        batch = pa.Batch(ctx, jobs, mode=mode)
+        try:
+            batch.capture()
+            for _ in range(3):
+                batch.run()
+            torch.cuda.synchronize()
+            s.record()
+            reps = 10
+            for _ in range(reps):
+                batch.run()
+            e.record()
+            torch.cuda.synchronize()
+            if batch.result() != pa.PA_OK:
+                raise RuntimeError(f"{name} batch run reported a failure")
+            ms = s.elapsed_time(e) / reps
+            res[name] = {"ms": round(ms, 3), "mbps": round(bits / (ms * 1e-3) / 1e6, 1),
+                         "launches_per_run": batch.launches()}
+        finally:
+            batch.close()
+    res["grouped"]["runs"] = "one launch per pass per length group, groups on 4 streams, captured HIP graph"
+    res["persistent"] = "not run: the persistent queue kernel is switched off in this build"
     pa.pa_reserve(ctx, max(b.n for b in blocks))
     for b, j in zip(blocks, jobs):
         pa.pa_hash_async(ctx, j["key"], b.seed_a, b.seed_b, b.n, b.m, j["out"])
@@ -348,13 +359,9 @@ def batched_vs_plain(pa, ctx, torch, workloads):
     e.record()
     torch.cuda.synchronize()
     ms_plain = s.elapsed_time(e)
-    return {"workload": "256 blocks, n log-uniform in [1e5, 1e7], m = round(r n), "
-                        "r uniform in [0.05, 0.5], seed 3",
-            "bits": bits, "batched_ms": round(ms_batch, 3),
-            "batched_mbps": round(bits / (ms_batch * 1e-3) / 1e6, 1),
-            "plain_ms": round(ms_plain, 3),
-            "plain_mbps": round(bits / (ms_plain * 1e-3) / 1e6, 1),
-            "batch_runs": "captured HIP graph, groups by transform length on 4 streams"}
+    res["plain"] = {"ms": round(ms_plain, 3), "mbps": round(bits / (ms_plain * 1e-3) / 1e6, 1),
+                    "runs": "pa_hash_async per block, one stream"}
+    return res
 
 
 def served(pa, torch, workloads, count):
@@ -462,6 +469,10 @@ def main():
                  for k, v in kinds.items()}
 
     extra = {}
+    if args.only_batch:
+        print(json.dumps(batched_vs_plain(pa, ctx, torch, workloads)), flush=True)
+        pa.pa_destroy(ctx)
+        return
     if not args.no_extra:
         b6 = workloads.single("n1e6")
         ms6, _, _ = time_single(pa, ctx, torch, b6, 200, 500)

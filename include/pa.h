@@ -174,9 +174,24 @@ int pa_hash_mul_async(pa_ctx *ctx, const pa_mul *mul, const uint64_t *d_key, uin
 void pa_mul_destroy(pa_mul *mul);
 
 /*
- * Batches: many blocks of uneven n in one sequence of launches.  Blocks are
- * grouped by transform length; every kernel of a group runs once for all of
- * the group's blocks.  All pointers in a pa_job are device memory.
+ * Batches: many blocks of uneven n hashed together.  Blocks are grouped by
+ * transform length (and digit layout).  Two ways to run them:
+ *   PA_BATCH_GROUPED (the default): every kernel of a group is one launch for
+ *     all of the group's blocks; groups run on side streams.
+ *   PA_BATCH_PERSISTENT (switched off in this build: creating such a batch
+ *     returns PA_EINVAL until the kernel has been validated on the GPU): one
+ *     persistent kernel runs everything.
+ *     Its workgroups, as many as fit on the device at once, take work items
+ *     (one pass tile of one prime of one block, or one carry chunk of one
+ *     block) from a device queue in dependency order.  Each item waits until
+ *     the items its block needs are done (per-block counters), so different
+ *     blocks' passes and carries overlap with no launch boundaries between
+ *     them.  The waits are bounded; a run whose wait gave up is reported by
+ *     pa_batch_result (never expected; it would leave outputs incomplete).
+ * Both compute the same bits as hashing each block alone (the per-block
+ * method of Section 2.3, eq. (6), batched).  A group uses the geometry that
+ * pa_tune or pa_plan_set chose for its length on the context, if any; else a
+ * default for many blocks.  All pointers in a pa_job are device memory.
  *   key:  ceil(n/64) words;  out: ceil(m/64) words
  *   c, d: explicit operands (ceil(n/64) words each) or NULL to expand them
  *         from seed_a / seed_b; an explicit c must be odd (eq. (6))
@@ -207,6 +222,24 @@ typedef struct pa_batch pa_batch;
  */
 int pa_batch_create(pa_ctx *ctx, pa_job *jobs, size_t count, pa_batch **batch);
 
+/* Batch options.  NULL gives the defaults (grouped). */
+#define PA_BATCH_PERSISTENT 0
+#define PA_BATCH_GROUPED 1
+typedef struct pa_batch_opts {
+    int mode;              /* PA_BATCH_PERSISTENT or PA_BATCH_GROUPED */
+    uint32_t wait_us;      /* persistent: microseconds a dependency wait may take before the
+                            * run gives up (0: 2 s) */
+    int force_abort;       /* persistent, for testing the failure path: every wait for a
+                            * dependency gives up at once, and the run reports PA_EDEVICE */
+} pa_batch_opts;
+int pa_batch_create_ex(pa_ctx *ctx, pa_job *jobs, size_t count, const pa_batch_opts *opts,
+                       pa_batch **batch);
+
+/* After the stream of a run has completed: PA_OK, or PA_EDEVICE if the
+ * persistent kernel gave up a dependency wait (the outputs are then
+ * incomplete).  Needs the batch's context. */
+int pa_batch_result(const pa_batch *batch);
+
 /* Queue every kernel of the batch on `stream` (replays the captured graph if
  * pa_batch_capture was called).  Returns without waiting. */
 int pa_batch_run(pa_batch *batch, void *stream);
@@ -216,16 +249,18 @@ int pa_batch_run(pa_batch *batch, void *stream);
  * launch.  Nothing runs during the capture. */
 int pa_batch_capture(pa_batch *batch, void *stream);
 
-/* Device bytes the batch holds (workspace + job table). */
+/* Device bytes the batch holds (workspace, job table, persistent queue table). */
 uint64_t pa_batch_bytes(const pa_batch *batch);
 
-/* Number of blocks that will run, and of launches one run queues. */
+/* Number of blocks that will run, and of kernel launches one run queues
+ * (persistent: 2, the counter reset and the queue kernel). */
 size_t pa_batch_size(const pa_batch *batch);
 size_t pa_batch_launches(const pa_batch *batch);
 
 void pa_batch_destroy(pa_batch *batch);
 
-/* create + run + wait + destroy; per-block status in jobs[i].status. */
+/* create (grouped) + run + wait + pa_batch_result + destroy; per-block
+ * status in jobs[i].status. */
 int pa_hash_many(pa_ctx *ctx, pa_job *jobs, size_t count, void *stream);
 
 /*

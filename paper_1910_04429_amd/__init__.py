@@ -56,6 +56,14 @@ class _Job(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("status", ctypes.c_int)]
 
 
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("wait_us", ctypes.c_uint32),
+                ("force_abort", ctypes.c_int)]
+
+
+PA_BATCH_PERSISTENT, PA_BATCH_GROUPED = 0, 1
+
+
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int),
                 ("max_n", ctypes.c_uint64)]
@@ -135,6 +143,11 @@ _lib.pa_toeplitz_length.argtypes = [_u64, _u64, ctypes.POINTER(_u64)]
 _lib.pa_batch_create.restype = ctypes.c_int
 _lib.pa_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Job), ctypes.c_size_t,
                                  ctypes.POINTER(ctypes.c_void_p)]
+_lib.pa_batch_create_ex.restype = ctypes.c_int
+_lib.pa_batch_create_ex.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Job), ctypes.c_size_t,
+                                    ctypes.POINTER(_BatchOpts), ctypes.POINTER(ctypes.c_void_p)]
+_lib.pa_batch_result.restype = ctypes.c_int
+_lib.pa_batch_result.argtypes = [ctypes.c_void_p]
 _lib.pa_batch_run.restype = ctypes.c_int
 _lib.pa_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
 _lib.pa_batch_capture.restype = ctypes.c_int
@@ -403,15 +416,25 @@ def pa_hash_many(ctx, jobs, stream=None) -> list[int]:
 
 class Batch:
     """pa_batch: a planned batch whose launches can be replayed (and captured
-    into a HIP graph).  Keeps the job array alive with the batch."""
+    into a HIP graph).  Keeps the job array alive with the batch.  mode:
+    PA_BATCH_GROUPED (one launch per pass per length group) or
+    PA_BATCH_PERSISTENT (one queue kernel; refused by this build)."""
 
-    def __init__(self, ctx, jobs):
+    def __init__(self, ctx, jobs, mode: int = PA_BATCH_GROUPED, wait_us: int = 0,
+                 force_abort: bool = False):
         self.ctx = ctx
         self._jobs = _job_array(jobs)
         self._refs = jobs
+        opts = _BatchOpts(int(mode), int(wait_us), int(bool(force_abort)))
         h = ctypes.c_void_p()
-        _check(ctx, _lib.pa_batch_create(ctx, self._jobs, len(jobs), ctypes.byref(h)))
+        _check(ctx, _lib.pa_batch_create_ex(ctx, self._jobs, len(jobs), ctypes.byref(opts),
+                                            ctypes.byref(h)))
         self.h = h
+
+    def result(self) -> int:
+        """After the run's stream completed: PA_OK or PA_EDEVICE (a persistent
+        dependency wait gave up)."""
+        return int(_lib.pa_batch_result(self.h))
 
     @property
     def status(self) -> list[int]:

@@ -8,7 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpa.so")
-SOURCES = ["runtime.hip", "ntt.hip", "carry.hip", "toeplitz.hip", "server.hip"]
+SOURCES = ["runtime.hip", "ntt.hip", "carry.hip", "toeplitz.hip", "server.hip", "persist.hip"]
 ARCH = "gfx950"
 
 

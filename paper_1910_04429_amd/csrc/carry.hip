@@ -24,355 +24,16 @@
 // carry-in, redoes (1), resolves its digits (and two past its end) and writes
 // every output word that starts inside the chunk.  Workgroups on different
 // XCDs never exchange data inside a kernel.
-#include "carryfn.h"
-#include "kernels.h"
+#include "carry_body.h"
 
 namespace pa {
 namespace {
 
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
-{
-    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-// Inclusive scan of one function per lane over a wavefront, in lane order.
-__device__ __forceinline__ uint32_t wave_scan(uint32_t f, int lane)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t prev = __shfl_up(f, d);
-        if (lane >= d)
-            f = carry_compose(prev, f);
-    }
-    return f;
-}
-
-__device__ __forceinline__ uint32_t addend_digit(const CarryArgs& a, uint32_t t)
-{
-    if (t >= a.num_digits)
-        return 0;
-    uint32_t v;
-    if (a.addend_src == kSrcDigits) {
-        v = a.addend[t];
-    } else {
-        const uint64_t w = splitmix64(a.seed, t >> 1);
-        v = (t & 1) ? (uint32_t)(w >> 32) : (uint32_t)w;
-    }
-    const uint32_t top = (uint32_t)(a.n & 31);
-    if (t == a.num_digits - 1 && top)
-        v &= (1u << top) - 1u;
-    return v;
-}
-
-// Exact coefficient from its residues over the first NP primes (Garner's mixed
-// radix, then Horner in 32-bit words): z[0..NP), least significant first.
-template <int NP>
-__device__ __forceinline__ void crt(const uint32_t (&r)[NP], uint32_t (&z)[NP])
-{
-    uint32_t v[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        const uint32_t p = kPrimes[i];
-        uint32_t t = r[i];
-#pragma unroll
-        for (int j = 0; j < i; ++j) {
-            // v_j < p_j < 2 p_i (every prime is above 2^30): reduce it, then
-            // t + p - v_j < 2 p < 2^32 goes into Shoup's multiply unreduced
-            const uint32_t vj = (kPrimes[j] > p) ? min(v[j], v[j] - p) : v[j];
-            t = fmul_shoup(t + p - vj, kGarner.inv[i][j], kGarner.q[i][j], p);
-        }
-        v[i] = t;
-    }
-    z[0] = v[NP - 1];
-#pragma unroll
-    for (int i = NP - 2; i >= 0; --i) {
-        const int words = NP - 1 - i;             // words of the accumulator so far
-        uint64_t carry = v[i];
-#pragma unroll
-        for (int w = 0; w < words; ++w) {
-            const uint64_t t = (uint64_t)z[w] * kPrimes[i] + carry;   // < 2^63 + 2^32
-            z[w] = (uint32_t)t;
-            carry = t >> 32;
-        }
-        z[words] = (uint32_t)carry;
-    }
-}
-
-// Chunk-local digit i in [0, kChunk + 2) <-> LDS slot of the resolved digit,
-// padded so that threads writing consecutive runs of kPer digits hit distinct
-// banks.
-template <int kPer>
-__device__ __forceinline__ int slot(int i)
-{
-    return i + i / kPer;
-}
-
-// Batch mode: take the block's sizes, addend, state and output from its job.
-__device__ __forceinline__ void bind_job(CarryArgs& a, uint32_t job)
-{
-    const JobDesc& j = a.jobs[job];
-    a.res = j.B;
-    a.num_digits = j.num_digits;
-    a.n = j.n;
-    a.m = j.m;
-    if (j.d) {
-        a.addend_src = kSrcDigits;
-        a.addend = j.d;
-    } else {
-        a.addend_src = kSrcSeed;
-        a.seed = j.seed_b;
-    }
-    a.desc = j.carry;
-    a.out = j.out;
-    a.chunks = j.chunks;
-}
-
-// Residues of coefficient K (0 outside [0, ceil(D / W))).
-template <int W>
-__device__ __forceinline__ void load_res(const CarryArgs& a, int64_t K, uint32_t (&r)[2 * W + 1])
-{
-    const int64_t coeffs = (a.num_digits + W - 1) / W;
-#pragma unroll
-    for (int pi = 0; pi < 2 * W + 1; ++pi)
-        r[pi] = (K < 0 || K >= coeffs) ? 0u : a.res[(size_t)pi * a.L + K];
-}
-
-// Exact coefficient K (0 outside the product's coefficients).
-template <int W>
-__device__ __forceinline__ void load_coeff(const CarryArgs& a, int64_t K, uint32_t (&z)[2 * W + 1])
-{
-    uint32_t r[2 * W + 1];
-    load_res<W>(a, K, r);
-    crt<2 * W + 1>(r, z);
-}
-
-// kApply = false: write the chunk's carry function.  kApply = true: resolve the
-// chunk with its carry-in and write its output words.
 template <int kPer, bool kApply, int W>
 __global__ __launch_bounds__(kCarryThreads) void k_carry(CarryArgs a)
 {
-    constexpr int NP = 2 * W + 1;              // primes, and words per coefficient
-    static_assert(kPer % W == 0, "a thread owns whole coefficients");
-    if (a.jobs) {
-        bind_job(a, blockIdx.y);
-        if (blockIdx.x >= a.chunks)
-            return;
-    }
-    constexpr int kChunk = kCarryThreads * kPer;
-    constexpr int kSlots = kChunk + 2 + (kChunk + 2) / kPer + 1;
-    __shared__ uint32_t val[kSlots];
-
-    const int tid = threadIdx.x;
-    const uint32_t chunk = blockIdx.x;
-    const int64_t k0 = (int64_t)chunk * kChunk;
-    const uint32_t D = a.num_digits;
-    // A chunk below bit n - m writes no output word (none starts in it): its
-    // digits reach the output only through its carry function, which the local
-    // kernel has written.
-    if (kApply && (uint64_t)(k0 + kChunk) * 32 <= a.n - a.m)
-        return;
-
-    // column sums of this thread's kPer digits (and, for the last thread, the
-    // two digits past the chunk, which it resolves with the chunk's carry-out);
-    // its digits W K + r come from coefficients K, K - 1 and K - 2
-    constexpr int kExtra = 2;
-    constexpr int kCo = kPer / W;              // coefficients per thread
-    uint64_t s[kPer + kExtra];
-    const int first = tid * kPer;
-    const int count = kPer + (tid == kCarryThreads - 1 ? kExtra : 0);
-    const int64_t kf = k0 + first;             // a multiple of W
-    const int64_t K0 = kf / W;
-    const int64_t coeffs = (D + W - 1) / W;
-    // this thread's residues, vector loads when its coefficients lie inside
-    // (K0 is a multiple of kCo, so they are aligned)
-    uint32_t r[NP][kCo];
-    if (K0 + kCo <= coeffs) {
-#pragma unroll
-        for (int pi = 0; pi < NP; ++pi) {
-            const uint32_t* src = a.res + (size_t)pi * a.L + K0;
-            if constexpr (kCo == 2) {
-                const uint2 q = *reinterpret_cast<const uint2*>(src);
-                r[pi][0] = q.x;
-                r[pi][1] = q.y;
-            } else {
-#pragma unroll
-                for (int v = 0; v < kCo / 4; ++v) {
-                    const uint4 q = reinterpret_cast<const uint4*>(src)[v];
-                    r[pi][4 * v] = q.x;
-                    r[pi][4 * v + 1] = q.y;
-                    r[pi][4 * v + 2] = q.z;
-                    r[pi][4 * v + 3] = q.w;
-                }
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < kCo; ++i) {
-            uint32_t q[NP];
-            load_res<W>(a, K0 + i, q);
-#pragma unroll
-            for (int pi = 0; pi < NP; ++pi) r[pi][i] = q[pi];
-        }
-    }
-    // Exact coefficients of this thread.  The high words of the two before its
-    // first come from the previous thread through LDS; for thread 0 they are
-    // the chunk's boundary coefficients, and the last thread's two extra digits
-    // need the coefficient past the chunk: lane 0 of waves 1, 2 and 3 computes
-    // one each, so that no wave runs more than one CRT beyond its own.
-    uint32_t z[kCo][NP];
-#pragma unroll
-    for (int ci = 0; ci < kCo; ++ci) {
-        uint32_t q[NP];
-#pragma unroll
-        for (int pi = 0; pi < NP; ++pi) q[pi] = r[pi][ci];
-        crt<NP>(q, z[ci]);
-    }
-    // hw[t + 1] = words W .. 2 W of thread t's last coefficient, then word 2 W
-    // of the one before it; hw[0] the same for the two coefficients before the
-    // chunk
-    constexpr int kHw = W + 2;
-    __shared__ uint32_t hw[kCarryThreads + 1][kHw];
-    __shared__ uint32_t tail[2];
-    static_assert(kCarryThreads == 256, "boundary coefficients go to waves 1, 2 and 3");
-#pragma unroll
-    for (int w = 0; w <= W; ++w) hw[tid + 1][w] = z[kCo - 1][W + w];
-    hw[tid + 1][W + 1] = z[kCo - 2][2 * W];
-    {
-        const int64_t Kc = k0 / W;             // first coefficient of the chunk
-        uint32_t q[NP];
-        if (tid == 64) {
-            load_coeff<W>(a, Kc - 1, q);
-#pragma unroll
-            for (int w = 0; w <= W; ++w) hw[0][w] = q[W + w];
-        } else if (tid == 128) {
-            load_coeff<W>(a, Kc - 2, q);
-            hw[0][W + 1] = q[2 * W];
-        } else if (tid == 192) {
-            load_coeff<W>(a, Kc + kChunk / W, q);
-            tail[0] = q[0];
-            tail[1] = q[1];
-        }
-    }
-    __syncthreads();
-    {
-        // prev[w] = word W + w of the previous coefficient (w <= W), prev2 =
-        // word 2 W of the one before it
-        uint32_t prev[W + 1];
-#pragma unroll
-        for (int w = 0; w <= W; ++w) prev[w] = hw[tid][w];
-        uint32_t prev2 = hw[tid][W + 1];
-#pragma unroll
-        for (int ci = 0; ci < kCo + 1; ++ci) {
-            const bool own = ci < kCo;
-#pragma unroll
-            for (int rr = 0; rr < W; ++rr) {
-                const int i = W * ci + rr;
-                if (i < count && i < kPer + kExtra) {
-                    const uint32_t zw = own ? z[ci % kCo][rr] : (rr < 2 ? tail[rr % 2] : 0u);
-                    const int64_t k = kf + i;
-                    const uint32_t d = (k < (int64_t)D) ? addend_digit(a, (uint32_t)k) : 0u;
-                    s[i % (kPer + kExtra)] = (k < (int64_t)D)
-                        ? (uint64_t)zw + prev[rr] + (rr == 0 ? prev2 : 0u) + d : 0ull;
-                }
-            }
-            if (own) {
-                prev2 = prev[W];
-#pragma unroll
-                for (int w = 0; w <= W; ++w) prev[w] = z[ci % kCo][W + w];
-            }
-        }
-    }
-    uint32_t f = carry_fn_of_sum(s[0]);
-#pragma unroll
-    for (int i = 1; i < kPer; ++i)
-        f = carry_compose(f, carry_fn_of_sum(s[i]));
-
-    // inclusive scan of the thread functions in thread order: within each
-    // wavefront by lane shuffles, then across the four wavefronts through LDS
-    const int lane = tid & 63, wave = tid >> 6;
-    f = wave_scan(f, lane);
-    __shared__ uint32_t wtot[kCarryThreads / 64];
-    if (lane == 63)
-        wtot[wave] = f;
-    __syncthreads();
-    uint32_t before = kCarryIdentity;              // the wavefronts before this one
-    for (int w = 0; w < wave; ++w)
-        before = carry_compose(before, wtot[w]);
-
-    if (!kApply) {
-        if (tid == kCarryThreads - 1)
-            a.desc[chunk] = carry_compose(before, f);
-        return;
-    }
-    // carry entering this chunk: the functions of chunks 0 .. chunk-1 (written
-    // by the local kernel) composed in order and applied to carry 0; each
-    // workgroup reads the few thousand bytes itself instead of waiting for a
-    // separate scan launch
-    __shared__ uint32_t wpre[kCarryThreads / 64];
-    uint32_t cin_chunk;
-    {
-        const uint32_t per_t = (chunk + kCarryThreads - 1) / kCarryThreads;
-        const uint32_t lo = (uint32_t)tid * per_t;
-        uint32_t g = kCarryIdentity;
-        for (uint32_t k = lo; k < lo + per_t && k < chunk; ++k)
-            g = carry_compose(g, a.desc[k]);
-        g = wave_scan(g, lane);
-        if (lane == 63)
-            wpre[wave] = g;
-        __syncthreads();
-        uint32_t all = kCarryIdentity;
-#pragma unroll
-        for (int w = 0; w < kCarryThreads / 64; ++w)
-            all = carry_compose(all, wpre[w]);
-        cin_chunk = carry_apply(all, 0u);
-    }
-
-    // resolve this thread's digits; V digits of the chunk (and two past it) to LDS
-    uint32_t excl = __shfl_up(f, 1);          // inclusive scan of the lane before
-    if (lane == 0)
-        excl = kCarryIdentity;
-    uint64_t carry = carry_apply(carry_compose(before, excl), cin_chunk);
-    const uint32_t top = (uint32_t)(a.n & 31);
-#pragma unroll
-    for (int i = 0; i < kPer + kExtra; ++i) {
-        if (i < count) {
-            const int li = first + i;
-            const int64_t k = k0 + li;
-            const uint64_t t = s[i] + carry;
-            uint32_t v = (uint32_t)t;
-            carry = t >> 32;
-            if (k >= (int64_t)D)
-                v = 0;
-            else if (k == (int64_t)D - 1 && top)
-                v &= (1u << top) - 1u;
-            val[slot<kPer>(li)] = v;
-        }
-    }
-    __syncthreads();
-
-    // output words whose first bit lies in this chunk: word j starts at bit
-    // b_j = n - m + 64 j, in digit b_j / 32
-    const uint64_t words = (a.m + 63) >> 6;
-    const uint64_t base = a.n - a.m;
-    const uint64_t lo_bit = (uint64_t)k0 * 32, hi_bit = lo_bit + (uint64_t)kChunk * 32;
-    const uint64_t j_lo = lo_bit > base ? (lo_bit - base + 63) >> 6 : 0;
-    uint64_t j_hi = hi_bit > base ? (hi_bit - base + 63) >> 6 : 0;
-    if (j_hi > words) j_hi = words;
-    for (uint64_t j = j_lo + tid; j < j_hi; j += kCarryThreads) {
-        const uint64_t bit = base + 64 * j;
-        const int q = (int)((bit >> 5) - (uint64_t)k0);   // in [0, kChunk)
-        const uint32_t sh = (uint32_t)(bit & 31);
-        const uint64_t v0 = val[slot<kPer>(q)], v1 = val[slot<kPer>(q + 1)],
-                       v2 = val[slot<kPer>(q + 2)];
-        uint64_t w = (v0 | (v1 << 32)) >> sh;
-        if (sh) w |= v2 << (64 - sh);
-        if (j == words - 1 && (a.m & 63))
-            w &= (1ull << (a.m & 63)) - 1ull;
-        a.out[j] = w;
-    }
+    __shared__ CarryShared<kPer, W> sh;
+    carry_chunk<kPer, kApply, W>(a, blockIdx.x, blockIdx.y, sh);
 }
 
 }  // namespace

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "context.h"
+#include "persist.h"
 
 using namespace pa;
 
@@ -425,9 +426,32 @@ void pass_geometry(PassArgs& a, const Plan& pl, int i)
     }
 }
 
-// Queue every kernel of the hash (or of one batch group) on `stream`.
+// The launches of a batch recorded for the persistent kernel instead of being
+// launched: each with the launches it depends on (indices in `launches`) and
+// its level, the longest dependency chain before it.
+struct PersistBuild {
+    std::vector<PersistLaunch> launches;
+    std::vector<int> level;
+    uint32_t lds = 0;              // dynamic LDS the largest item needs
+
+    int add(const PersistLaunch& l, int dep0, int dep1)
+    {
+        PersistLaunch x = l;
+        x.dep0 = dep0;
+        x.dep1 = dep1;
+        int lv = 0;
+        if (dep0 >= 0) lv = std::max(lv, level[dep0] + 1);
+        if (dep1 >= 0) lv = std::max(lv, level[dep1] + 1);
+        launches.push_back(x);
+        level.push_back(lv);
+        return (int)launches.size() - 1;
+    }
+};
+
+// Queue every kernel of the hash (or of one batch group) on `stream`, or, with
+// `pb`, record them as launches of the persistent batch kernel.
 int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
-                 Recorder* rec = nullptr)
+                 Recorder* rec = nullptr, PersistBuild* pb = nullptr)
 {
     const unsigned batch = w.batch;
     const uint64_t L = pl.L;
@@ -447,6 +471,21 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     base.dwords = pl.W;
     auto geometry = [&](PassArgs& a, int i) { pass_geometry(a, pl, i); };
     const uint32_t limit = (uint32_t)((coeffs_of(w.n, pl.W) + 3) & ~3ull);
+    // persistent recording: the launch as queue items, and the last launch
+    // of the multiplier's and of the key's (then the product's) chain
+    int prev_c = -1, prev_x = -1;
+    auto persist_pass = [&](const PassArgs& a, unsigned z) {
+        PersistLaunch l{};
+        l.kind = kPersistPass;
+        l.W = pl.W;
+        const uint32_t N = ((uint32_t)a.f << a.r) << a.logC;
+        l.gx = (uint32_t)(L / N);
+        l.gy = (uint32_t)NP;
+        l.gz = z;
+        l.pass = a;
+        pb->lds = std::max<uint32_t>(pb->lds, 4u * N);
+        return l;
+    };
 
     // The first passes of c and of x share their geometry and are independent:
     // one launch runs both (grid.z = 2), so each fills the other's last wave.
@@ -485,6 +524,10 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
             outb += arr;
             z = 2;
         }
+        if (pb) {
+            prev_c = pb->add(persist_pass(a, z), prev_c, -1);
+            continue;
+        }
         PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + outb, launch_pass(a, stream, z, ev_));
     }
     if (w.only_chat) return PA_OK;
@@ -506,6 +549,11 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
             in += arr;
             if (P == 1) outb = outD;
         }
+        if (pb) {
+            // the fused pass also reads c-hat
+            prev_x = pb->add(persist_pass(a, batch), prev_x, i == P - 1 ? prev_c : -1);
+            continue;
+        }
         PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, in + outb, launch_pass(a, stream, batch, ev_));
     }
     for (int i = P - 2; i >= 0; --i) {                      // remaining inverse passes
@@ -518,6 +566,10 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
         if (i == 0) {
             a.store_limit = limit;
             a.limit_to_digits = 1;
+        }
+        if (pb) {
+            prev_x = pb->add(persist_pass(a, batch), prev_x, -1);
+            continue;
         }
         PA_LAUNCH(ctx, rec, PA_K_NTT_PASS, arr + (i == 0 ? outD : arr),
                   launch_pass(a, stream, batch, ev_));
@@ -542,6 +594,20 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     ca.out = w.out;
     ca.jobs = w.jobs;
     const uint64_t chunk_bytes = 4ull * w.chunks * batch;
+    if (pb) {
+        PersistLaunch l{};
+        l.W = pl.W;
+        l.gx = w.chunks;
+        l.gy = 1;
+        l.gz = batch;
+        l.carry = ca;
+        l.kind = kPersistCarryLocal;
+        const int local = pb->add(l, prev_x, -1);
+        l.kind = kPersistCarryApply;
+        pb->add(l, local, -1);
+        pb->lds = std::max(pb->lds, persist_carry_lds_bytes(pl.W));
+        return PA_OK;
+    }
     PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + chunk_bytes, launch_carry_local(ca, stream, batch, ev_));
     PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, NP * 4ull * w.window + chunk_bytes + w.out_bytes,
               launch_carry_apply(ca, stream, batch, ev_));
@@ -660,6 +726,10 @@ int scratch_address(pa_ctx* ctx, int device, uint8_t** out)
 
 }  // namespace
 
+#ifndef PA_ENABLE_PERSISTENT
+#define PA_ENABLE_PERSISTENT 0
+#endif
+
 struct pa_batch {
     pa_ctx* ctx = nullptr;
     int device = 0;      // for pa_batch_destroy, which may follow pa_destroy(ctx)
@@ -678,11 +748,98 @@ struct pa_batch {
     size_t launches = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // persistent mode: the launch table, the queue counters, the grid, and the
+    // abort flag of the last run copied to host memory
+    int mode = PA_BATCH_GROUPED;
+    PersistLaunch* d_launch = nullptr;
+    uint32_t* d_ctr = nullptr;
+    uint32_t* h_abort = nullptr;
+    PersistArgs pargs{};
+    uint32_t workgroups = 0, lds = 0;
+    uint64_t table_bytes = 0;
 };
 
 namespace {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Geometry of a batch group of `blocks` blocks of length len: the context's
+// tuned or set geometry for that length, else the batch default (larger
+// tiles when many blocks fill the device together).
+bool batch_plan(const pa_ctx* ctx, Len len, unsigned blocks, Plan* pl)
+{
+    const int i = len_slot(len);
+    if (i < pa_ctx::kPlanSlots && ctx->plans[i].t) {
+        const PlanParams pp{ctx->plans[i].t, ctx->plans[i].ts, ctx->plans[i].r0};
+        if (make_plan(len, pl, blocks, pp)) return true;
+    }
+    return make_plan(len, pl, blocks);
+}
+
+// Record every group's launches as queue items, order them by level (then as
+// recorded: group by group, largest transforms first), number the items and
+// the per-block done counters, and upload the table.
+int build_persistent(pa_batch* b, const pa_batch_opts* opts)
+{
+    pa_ctx* ctx = b->ctx;
+    PersistBuild pb;
+    for (size_t gi = b->groups.size(); gi-- > 0;) {
+        const auto& g = b->groups[gi];
+        Work w;
+        w.jobs = b->d_jobs + g.first;
+        w.batch = g.count;
+        w.chunks = g.chunks;
+        w.per = g.per;
+        int rc = enqueue_plan(ctx, g.plan, w, nullptr, nullptr, &pb);
+        if (rc) return rc;
+    }
+    const size_t nl = pb.launches.size();
+    std::vector<int> order(nl);
+    for (size_t i = 0; i < nl; ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return pb.level[x] < pb.level[y]; });
+    std::vector<int> pos(nl);
+    for (size_t k = 0; k < nl; ++k) pos[order[k]] = (int)k;
+    std::vector<PersistLaunch> table(nl);
+    uint64_t items = 0, counters = 0;
+    for (size_t k = 0; k < nl; ++k) {
+        PersistLaunch l = pb.launches[order[k]];
+        l.dep0 = l.dep0 >= 0 ? pos[l.dep0] : -1;
+        l.dep1 = l.dep1 >= 0 ? pos[l.dep1] : -1;
+        l.first = (uint32_t)items;
+        l.ctr_base = (uint32_t)counters;
+        items += (uint64_t)l.gx * l.gy * l.gz;
+        counters += l.gz;
+        table[k] = l;
+    }
+    if (items >= (1ull << 31) || counters >= (1ull << 28))
+        return fail(ctx, PA_EINVAL, "batch too large for the persistent queue");
+    b->lds = pb.lds;
+    PA_HIP(ctx, persist_grid(b->lds, ctx->device, &b->workgroups));
+    b->table_bytes = sizeof(PersistLaunch) * nl + 4ull * (kPersistCounters + counters);
+    hipError_t e;
+    if ((e = hipMalloc(&b->d_launch, sizeof(PersistLaunch) * nl)) != hipSuccess ||
+        (e = hipMalloc(&b->d_ctr, 4ull * (kPersistCounters + counters))) != hipSuccess)
+        return fail(ctx, PA_ENOMEM, "persistent batch table allocation", e);
+    if ((e = hipHostMalloc((void**)&b->h_abort, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess)
+        return fail(ctx, PA_ENOMEM, "pinned host flag", e);
+    *b->h_abort = 0;
+    PA_HIP(ctx, hipMemcpy(b->d_launch, table.data(), sizeof(PersistLaunch) * nl,
+                          hipMemcpyHostToDevice));
+    PersistArgs& a = b->pargs;
+    a.launches = b->d_launch;
+    a.nlaunch = (uint32_t)nl;
+    a.total = (uint32_t)items;
+    a.ctr = b->d_ctr;
+    a.ncounters = (uint32_t)counters;
+    // the wait bound in ticks of the device's constant-rate clock (kHz)
+    int clock_khz = 0;
+    PA_HIP(ctx, hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, ctx->device));
+    const uint64_t wait_us = (opts && opts->wait_us) ? opts->wait_us : 2000000u;
+    a.wait_ticks = wait_us * (uint64_t)(clock_khz > 0 ? clock_khz : 100000) / 1000u;
+    a.force_abort = opts ? opts->force_abort : 0;
+    return PA_OK;
+}
 
 // Groups are independent: they run concurrently on the context's side
 // streams, forked from and joined back into `stream` with events (this also
@@ -690,6 +847,12 @@ uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 int enqueue_batch(pa_batch* b, hipStream_t stream)
 {
     pa_ctx* ctx = b->ctx;
+    if (b->mode == PA_BATCH_PERSISTENT) {
+        PA_HIP(ctx, launch_persist(b->pargs, b->workgroups, b->lds, stream));
+        PA_HIP(ctx, hipMemcpyAsync(b->h_abort, b->d_ctr + 1, sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, stream));
+        return PA_OK;
+    }
     const int ns = (int)std::min<size_t>(b->groups.size(), pa_ctx::kSide);
     if (ns > 1) {
         PA_HIP(ctx, hipEventRecord(ctx->fork, stream));
@@ -1261,13 +1424,34 @@ void pa_batch_destroy(pa_batch* b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     (void)hipFree(b->d_jobs);
     (void)hipFree(b->ws);
+    (void)hipFree(b->d_launch);
+    (void)hipFree(b->d_ctr);
+    if (b->h_abort) (void)hipHostFree(b->h_abort);
     delete b;
 }
 
 int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
 {
+    return pa_batch_create_ex(ctx, jobs, count, nullptr, out);
+}
+
+int pa_batch_create_ex(pa_ctx* ctx, pa_job* jobs, size_t count, const pa_batch_opts* opts,
+                       pa_batch** out)
+{
     if (!ctx || !out || (!jobs && count)) return PA_EINVAL;
     *out = nullptr;
+    const int mode = opts ? opts->mode : PA_BATCH_GROUPED;
+    if (mode != PA_BATCH_PERSISTENT && mode != PA_BATCH_GROUPED)
+        return fail(ctx, PA_EINVAL, "unknown batch mode");
+#if !PA_ENABLE_PERSISTENT
+    // The persistent queue kernel hung in its first GPU runs (its queue loop
+    // was compiled so that one workgroup repeated one item forever); the
+    // corrected loop has not run on a GPU yet, so the mode stays off.
+    if (mode == PA_BATCH_PERSISTENT)
+        return fail(ctx, PA_EINVAL,
+                    "the persistent batch kernel is switched off in this build (not yet "
+                    "validated on the GPU); use PA_BATCH_GROUPED");
+#endif
     PA_HIP(ctx, hipSetDevice(ctx->device));
     // validate
     std::vector<size_t> ok;
@@ -1301,6 +1485,7 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
     b->ctx = ctx;
     b->device = ctx->device;
     b->valid = ok.size();
+    b->mode = mode;
     // groups and workspace layout
     std::vector<JobDesc> h(ok.size());
     std::vector<uint64_t> offA(ok.size()), offC(ok.size());
@@ -1314,14 +1499,15 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
             ++e;
         }
         pa_batch::Group g;
-        if (!make_plan(plan_len(jobs[ok[i]].n), &g.plan, (unsigned)(e - i))) {
+        if (!batch_plan(ctx, plan_len(jobs[ok[i]].n), (unsigned)(e - i), &g.plan)) {
             delete b;
             return fail(ctx, PA_EINVAL, "internal: bad pass plan");
         }
         g.first = (uint32_t)i;
         g.count = (uint32_t)(e - i);
         const int W = g.plan.W;
-        g.per = carry_digits_per_thread((uint32_t)maxD, W);
+        g.per = mode == PA_BATCH_PERSISTENT ? (W == 3 ? kPersistPer3 : kPersistPer2)
+                                            : carry_digits_per_thread((uint32_t)maxD, W);
         const uint64_t chunk = (uint64_t)kCarryThreads * g.per;
         const uint64_t arr = align256((2ull * W + 1) * 4ull * g.plan.L);
         for (size_t k = i; k < e; ++k) {
@@ -1353,6 +1539,7 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
     }
     b->launches = 0;
     for (const auto& g : b->groups) b->launches += 3 * g.plan.P - 1 + 3;
+    if (mode == PA_BATCH_PERSISTENT) b->launches = 2;   // counter reset + the queue kernel
     hipError_t e;
     if ((e = hipMalloc(&b->ws, bytes)) != hipSuccess ||
         (e = hipMalloc(&b->d_jobs, sizeof(JobDesc) * h.size())) != hipSuccess) {
@@ -1369,6 +1556,13 @@ int pa_batch_create(pa_ctx* ctx, pa_job* jobs, size_t count, pa_batch** out)
         hipSuccess) {
         pa_batch_destroy(b);
         return fail(ctx, PA_EDEVICE, "batch job table upload", e);
+    }
+    if (mode == PA_BATCH_PERSISTENT) {
+        const int rc = build_persistent(b, opts);
+        if (rc) {
+            pa_batch_destroy(b);
+            return rc;
+        }
     }
     *out = b;
     return PA_OK;
@@ -1416,7 +1610,7 @@ int pa_batch_capture(pa_batch* b, void* stream)
 
 uint64_t pa_batch_bytes(const pa_batch* b)
 {
-    return b ? b->ws_bytes + sizeof(JobDesc) * b->valid : 0;
+    return b ? b->ws_bytes + sizeof(JobDesc) * b->valid + b->table_bytes : 0;
 }
 
 size_t pa_batch_size(const pa_batch* b) { return b ? b->valid : 0; }
@@ -1430,9 +1624,23 @@ int pa_hash_many(pa_ctx* ctx, pa_job* jobs, size_t count, void* stream)
     if (rc) return rc;
     rc = pa_batch_run(b, stream);
     const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (!rc && e == hipSuccess) rc = pa_batch_result(b);
     pa_batch_destroy(b);
-    if (rc) return rc;
+    if (rc) {
+        for (size_t i = 0; i < count; ++i)
+            if (jobs[i].status == PA_OK) jobs[i].status = rc;
+        return rc;
+    }
     if (e != hipSuccess) return fail(ctx, PA_EDEVICE, "hipStreamSynchronize", e);
+    return PA_OK;
+}
+
+int pa_batch_result(const pa_batch* b)
+{
+    if (!b) return PA_EINVAL;
+    if (b->mode == PA_BATCH_PERSISTENT && b->h_abort && *(volatile uint32_t*)b->h_abort)
+        return fail(b->ctx, PA_EDEVICE,
+                    "persistent batch kernel: a dependency wait gave up; outputs are incomplete");
     return PA_OK;
 }
 

@@ -7,18 +7,10 @@
 // below the prime, so the residues are the coefficients themselves); these
 // kernels draw a seeded t and turn the coefficient residues into packed bits.
 #include "kernels.h"
+#include "splitmix.h"
 
 namespace pa {
 namespace {
-
-// SplitMix64 output i for `seed` (Steele, Lea and Flood, OOPSLA 2014).
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
-{
-    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
 
 __global__ __launch_bounds__(256) void k_stream_words(uint64_t seed, uint64_t words, uint64_t* out)
 {

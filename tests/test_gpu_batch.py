@@ -62,6 +62,14 @@ def small_mixed_batch(count=48, seed=11):
     return workloads.batch_blocks(seed, count, n_lo=1, n_hi=3e5, r_lo=0.01, r_hi=1.0)
 
 
+def test_persistent_mode_is_refused(pa, ctx):
+    blocks = small_mixed_batch(4, seed=23)
+    with pytest.raises(pa.PAError) as e:
+        pa.Batch(ctx, _device_jobs(blocks), mode=pa.PA_BATCH_PERSISTENT)
+    assert e.value.status == pa.PA_EINVAL
+    assert "switched off" in pa.pa_last_error(ctx)
+
+
 def test_mixed_batch_against_oracle(pa, ctx):
     blocks = small_mixed_batch()
     _log(f"mixed batch: n in [{min(b.n for b in blocks)}, {max(b.n for b in blocks)}]")
@@ -152,3 +160,74 @@ def test_batch_workload_256_blocks(pa, ctx):
             assert np.array_equal(_host(j["out"]), _want(b)), (i, b.n, b.m)
     finally:
         batch.close()
+
+
+PERSISTENT_OFF = ("the persistent batch kernel hung in its first GPU runs; the cause (its queue "
+                  "loop compiled so that a workgroup repeated one item) is fixed in the source "
+                  "but not yet run on a GPU, so the library refuses the mode")
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+def test_persistent_and_grouped_modes_agree(pa, ctx):
+    """The persistent queue kernel and the grouped launches give the same bits
+    (and the oracle's) on a mixed batch, eagerly and through graph replays."""
+    import torch
+    blocks = small_mixed_batch(40, seed=21)
+    outs = {}
+    for mode in (pa.PA_BATCH_PERSISTENT, pa.PA_BATCH_GROUPED):
+        jobs = _device_jobs(blocks)
+        batch = pa.Batch(ctx, jobs, mode=mode)
+        try:
+            assert batch.launches() == (2 if mode == pa.PA_BATCH_PERSISTENT else batch.launches())
+            batch.run()
+            torch.cuda.synchronize()
+            assert batch.result() == pa.PA_OK
+            outs[mode] = [_host(j["out"]) for j in jobs]
+            batch.capture()
+            for rep in range(2):
+                for j in jobs:
+                    j["out"].fill_(-1)
+                torch.cuda.synchronize()
+                batch.run()
+                torch.cuda.synchronize()
+                assert batch.result() == pa.PA_OK
+                for e, j in zip(outs[mode], jobs):
+                    assert np.array_equal(_host(j["out"]), e), (mode, rep)
+        finally:
+            batch.close()
+    for b, p_out, g_out in zip(blocks, outs[pa.PA_BATCH_PERSISTENT], outs[pa.PA_BATCH_GROUPED]):
+        assert np.array_equal(p_out, g_out), (b.n, b.m)
+        assert np.array_equal(p_out, _want(b)), (b.n, b.m)
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+def test_persistent_wait_failure_is_reported(pa, ctx):
+    """Forced from the host: every dependency wait that would poll gives up at
+    once.  The kernel drains (every item is taken and counted) and the run is
+    reported as failed; the context and a normal batch still work after it."""
+    import torch
+    blocks = small_mixed_batch(16, seed=22)
+    jobs = _device_jobs(blocks)
+    batch = pa.Batch(ctx, jobs, force_abort=True)
+    try:
+        batch.run()
+        torch.cuda.synchronize()
+        assert batch.result() == pa.PA_EDEVICE
+    finally:
+        batch.close()
+    jobs = _device_jobs(blocks)
+    assert pa.pa_hash_many(ctx, jobs) == [pa.PA_OK] * len(blocks)
+    for b, j in zip(blocks, jobs):
+        assert np.array_equal(_host(j["out"]), _want(b)), (b.n, b.m)
+
+
+def test_large_blocks_and_both_layouts(pa, ctx):
+    """Blocks of both digit layouts (five and seven primes) and multi-pass
+    transforms in one batch, against the oracle."""
+    sizes = [(3_000_001, 1_000_003), (1_000_003, 99_999), (10_000_000, 2_000_000),
+             (131_073, 65_537), (6_000_011, 2_999_999), (64, 64)]
+    blocks = [workloads.single_block(100 + i, n, m) for i, (n, m) in enumerate(sizes)]
+    jobs = _device_jobs(blocks)
+    assert pa.pa_hash_many(ctx, jobs) == [pa.PA_OK] * len(blocks)
+    for b, j in zip(blocks, jobs):
+        assert np.array_equal(_host(j["out"]), _want(b)), (b.n, b.m)
