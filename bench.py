@@ -348,7 +348,7 @@ def batched_vs_plain(pa, ctx, torch, workloads):
         finally:
             batch.close()
     res["grouped"]["runs"] = "one launch per pass per length group, groups on 4 streams, captured HIP graph"
-    res["persistent"] = "not run: the persistent queue kernel is switched off in this build"
+    res["persistent"] = "not run: the persistent queue kernel is switched off (not yet validated on a GPU)"
     pa.pa_reserve(ctx, max(b.n for b in blocks))
     for b, j in zip(blocks, jobs):
         pa.pa_hash_async(ctx, j["key"], b.seed_a, b.seed_b, b.n, b.m, j["out"])

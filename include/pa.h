@@ -178,8 +178,8 @@ void pa_mul_destroy(pa_mul *mul);
  * transform length (and digit layout).  Two ways to run them:
  *   PA_BATCH_GROUPED (the default): every kernel of a group is one launch for
  *     all of the group's blocks; groups run on side streams.
- *   PA_BATCH_PERSISTENT (switched off in this build: creating such a batch
- *     returns PA_EINVAL until the kernel has been validated on the GPU): one
+ *   PA_BATCH_PERSISTENT (switched off: creating such a batch returns
+ *     PA_EINVAL until the kernel has been validated on a GPU): one
  *     persistent kernel runs everything.
  *     Its workgroups, as many as fit on the device at once, take work items
  *     (one pass tile of one prime of one block, or one carry chunk of one

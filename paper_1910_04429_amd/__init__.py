@@ -418,7 +418,7 @@ class Batch:
     """pa_batch: a planned batch whose launches can be replayed (and captured
     into a HIP graph).  Keeps the job array alive with the batch.  mode:
     PA_BATCH_GROUPED (one launch per pass per length group) or
-    PA_BATCH_PERSISTENT (one queue kernel; refused by this build)."""
+    PA_BATCH_PERSISTENT (one queue kernel; refused until validated on a GPU)."""
 
     def __init__(self, ctx, jobs, mode: int = PA_BATCH_GROUPED, wait_us: int = 0,
                  force_abort: bool = False):

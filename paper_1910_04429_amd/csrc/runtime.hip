@@ -1449,8 +1449,8 @@ int pa_batch_create_ex(pa_ctx* ctx, pa_job* jobs, size_t count, const pa_batch_o
     // corrected loop has not run on a GPU yet, so the mode stays off.
     if (mode == PA_BATCH_PERSISTENT)
         return fail(ctx, PA_EINVAL,
-                    "the persistent batch kernel is switched off in this build (not yet "
-                    "validated on the GPU); use PA_BATCH_GROUPED");
+                    "the persistent batch kernel is switched off (not yet validated on a "
+                    "GPU); use PA_BATCH_GROUPED");
 #endif
     PA_HIP(ctx, hipSetDevice(ctx->device));
     // validate
