@@ -36,8 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="n1e8", choices=["n1e6", "n1e7", "n1e8"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-single-thread", action="store_true",
-                    help="also time the oracle on one thread (about 25 s at n = 10^8)")
+    ap.add_argument("--no-cpu-single-thread", action="store_true",
+                    help="skip the oracle's single-thread leg (about 25 s at n = 10^8)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the n=1e6, batched and served measurements")
     ap.add_argument("--only-batch", action="store_true",
@@ -184,16 +184,39 @@ def ingest_counters(dirs, calib_mib, path=COUNTERS):
     return out
 
 
-def cpu_baseline(blk, key, single_thread=False):
+def progress(msg):
+    """One line per finished phase on stderr (the JSON line is the only stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(blk, key, single_thread=True):
+    """The oracle on the whole n = 10^8 block on this host: once with its
+    Karatsuba's top three levels split over 27 threads (at least one per
+    logical CPU of a 16-CPU host), once on one thread.  A reported baseline,
+    not a target: a Karatsuba low product, not GMP."""
     import oracle
-    cores = 9   # the oracle splits two Karatsuba levels onto 3 x 3 threads
+    ncpu = os.cpu_count() or 1
+    levels = 3                       # 3^3 = 27 threads
+    threads = 3 ** levels
     t0 = time.perf_counter()
-    y = oracle.pa_hash(key, blk.seed_a, blk.seed_b, blk.n, blk.m, par_levels=2)
+    y = oracle.pa_hash(key, blk.seed_a, blk.seed_b, blk.n, blk.m, par_levels=levels)
     dt = time.perf_counter() - t0
-    res = {"value": blk.n / dt / 1e6, "unit": "Mbps", "cores": cores, "kind": "oracle",
-           "sample": f"one full block n={blk.n} m={blk.m} ({dt:.2f} s), "
-                     f"Karatsuba low product on {cores} threads; host has "
-                     f"{os.cpu_count()} logical CPUs"}
+    res = {"value": blk.n / dt / 1e6, "unit": "Mbps", "cores": min(threads, ncpu),
+           "threads": threads, "kind": "oracle", "cpu": cpu_model(), "host_logical_cpus": ncpu,
+           "sample": f"one full block n={blk.n} m={blk.m} ({dt:.2f} s), Karatsuba low product "
+                     f"with its top {levels} levels on {threads} threads over the host's "
+                     f"{ncpu} logical CPUs"}
     if single_thread:
         t0 = time.perf_counter()
         y1 = oracle.pa_hash(key, blk.seed_a, blk.seed_b, blk.n, blk.m, par_levels=0)
@@ -207,14 +230,16 @@ def cpu_baseline(blk, key, single_thread=False):
 def time_single(pa, ctx, torch, blk, steps, warmup, plan=None):
     """ms per block for one block through pa_hash_async, key resident (the
     context's transform geometry for this length is autotuned first, unless
-    a plan is given)."""
+    a plan is given; the key is uploaded before, so that the warm-up follows
+    the tuner's device work without a pause)."""
+    d_key = torch.from_numpy(blk.key().view(np.int64)).cuda()
+    d_out = torch.zeros(pa.words(blk.m), dtype=torch.int64, device="cuda")
+    pa.pa_reserve(ctx, blk.n)
+    torch.cuda.synchronize()
     if plan is None:
         pa.pa_tune(ctx, blk.n, 8)
     else:
         pa.pa_plan_set(ctx, blk.n, plan)
-    d_key = torch.from_numpy(blk.key().view(np.int64)).cuda()
-    d_out = torch.zeros(pa.words(blk.m), dtype=torch.int64, device="cuda")
-    pa.pa_reserve(ctx, blk.n)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         pa.pa_hash_async(ctx, d_key, blk.seed_a, blk.seed_b, blk.n, blk.m, d_out, stream)
@@ -366,40 +391,65 @@ def batched_vs_plain(pa, ctx, torch, workloads):
 
 def served(pa, torch, workloads, count):
     """Poisson stream of requests, n log-uniform in [1e6, 1e8], m = 0.3 n.
-    Saturated throughput C first (all requests at t = 0), then offered loads
-    rho C for rho in (0.5, 0.8, 0.95)."""
+    Device-resident requests: saturated throughput C first (all requests at
+    t = 0), then offered loads rho C for rho in (0.5, 0.8, 0.95).  Then the same
+    requests from host memory (each latency includes the key's copy to the
+    device and the result's copy back): their own saturated throughput and the
+    same three loads of it.  Each request's key is its own window of one
+    seeded pool of 2^25 words (the hash does the same work on any key bits)."""
     blocks, unit_times = workloads.served_requests(4, count, rate_per_s=1.0)
-    pool = torch.from_numpy(workloads.key_bits(workloads.seeds_of(4)[0], 10**8)
-                            .view(np.int64)).cuda()
-    outs = [torch.zeros(workloads.words(b.m), dtype=torch.int64, device="cuda") for b in blocks]
-    jobs = [{"key": pool, "out": o, "n": b.n, "m": b.m, "seed_a": b.seed_a,
-             "seed_b": b.seed_b} for b, o in zip(blocks, outs)]
+    pool_words = 1 << 25
+    pool_host = workloads.key_bits(workloads.seeds_of(4)[0], 64 * pool_words)
+    rng = np.random.default_rng(4)
+    # even word offsets keep every key 16-byte aligned, as a fresh allocation is
+    offs = [2 * int(rng.integers(0, (pool_words - workloads.words(b.n)) // 2 + 1)) for b in blocks]
+    pool = torch.from_numpy(pool_host.view(np.int64)).cuda()
+    dev_jobs = [{"key": pool[o: o + workloads.words(b.n)],
+                 "out": torch.zeros(workloads.words(b.m), dtype=torch.int64, device="cuda"),
+                 "n": b.n, "m": b.m, "seed_a": b.seed_a, "seed_b": b.seed_b}
+                for b, o in zip(blocks, offs)]
+    host_jobs = [{"key": pool_host[o: o + workloads.words(b.n)],
+                  "out": np.zeros(workloads.words(b.m), dtype=np.uint64),
+                  "n": b.n, "m": b.m, "seed_a": b.seed_a, "seed_b": b.seed_b}
+                 for b, o in zip(blocks, offs)]
+    torch.cuda.synchronize()
     mean_n = sum(b.n for b in blocks) / len(blocks)
     budget = 16 << 30
     res = {"workload": f"{count} requests, n log-uniform in [1e6, 1e8], m = 0.3 n, "
-                       "Poisson arrivals, seed 4; keys are prefixes of one resident "
-                       "1e8-bit key, seeds per request",
-           "hbm_budget_bytes": budget, "slots": 8, "loads": []}
-    with pa.Server(hbm_budget=budget, slots=8, max_n=10**8) as srv:
-        lat, st = srv.run_trace(jobs[:64], [0.0] * 64)            # warm-up
-    with pa.Server(hbm_budget=budget, slots=8, max_n=10**8) as srv:
-        lat, st = srv.run_trace(jobs, [0.0] * len(jobs))
-        sat = srv.stats()
-    C = sat["bits"] / sat["wall_s"]
-    res["saturated_mbps"] = round(C / 1e6, 1)
-    for rho in (0.5, 0.8, 0.95):
-        rate = rho * C / mean_n                                     # requests per second
-        times = np.asarray(unit_times) / rate
+                       "Poisson arrivals, seed 4; each key a window of a seeded 2^31-bit pool, "
+                       "seeds per request",
+           "hbm_budget_bytes": budget, "slots": 8}
+
+    def run(jobs, device):
+        out = {"loads": []}
         with pa.Server(hbm_budget=budget, slots=8, max_n=10**8) as srv:
-            lat, st = srv.run_trace(jobs, times)
-            s = srv.stats()
-        ok = all(x == pa.PA_OK for x in st)
-        res["loads"].append({"rho": rho, "offered_mbps": round(rho * C / 1e6, 1),
-                             "mbps": round(s["bits"] / s["wall_s"] / 1e6, 1),
-                             "p50_ms": round(s["lat_p50_ms"], 3),
-                             "p99_ms": round(s["lat_p99_ms"], 3),
-                             "mean_ms": round(s["lat_mean_ms"], 3),
-                             "peak_inflight": s["peak_inflight"], "all_ok": ok})
+            srv.run_trace(jobs[:64], [0.0] * 64, device=device)          # warm-up
+        with pa.Server(hbm_budget=budget, slots=8, max_n=10**8) as srv:
+            srv.run_trace(jobs, [0.0] * len(jobs), device=device)
+            sat = srv.stats()
+        C = sat["bits"] / sat["wall_s"]
+        out["saturated_mbps"] = round(C / 1e6, 1)
+        for rho in (0.5, 0.8, 0.95):
+            rate = rho * C / mean_n                                     # requests per second
+            times = np.asarray(unit_times) / rate
+            with pa.Server(hbm_budget=budget, slots=8, max_n=10**8) as srv:
+                lat, st = srv.run_trace(jobs, times, device=device)
+                s = srv.stats()
+            out["loads"].append({"rho": rho, "offered_mbps": round(rho * C / 1e6, 1),
+                                 "mbps": round(s["bits"] / s["wall_s"] / 1e6, 1),
+                                 "p50_ms": round(s["lat_p50_ms"], 3),
+                                 "p99_ms": round(s["lat_p99_ms"], 3),
+                                 "mean_ms": round(s["lat_mean_ms"], 3),
+                                 "peak_inflight": s["peak_inflight"],
+                                 "all_ok": all(x == pa.PA_OK for x in st)})
+        return out
+
+    dev = run(dev_jobs, True)
+    res["saturated_mbps"] = dev["saturated_mbps"]
+    res["loads"] = dev["loads"]
+    res["host_data"] = run(host_jobs, False)
+    res["host_data"]["note"] = ("key and result in host memory: latency from arrival to the "
+                                "result in host memory, copies included")
     return res
 
 
@@ -436,6 +486,7 @@ def main():
         plan = {"tile_log": t, "strided_tile_log": ts, "rows3_log": r0}
     ms_per_step, d_key, d_out = time_single(pa, ctx, torch, blk, args.steps, args.warmup, plan)
     wall = time.perf_counter() - t0
+    progress(f"{args.workload}: {ms_per_step:.4f} ms per step")
     mbps = blk.n / (ms_per_step * 1e-3) / 1e6
     latency = per_block_latency(pa, ctx, torch, blk, d_key, d_out)
     gpu_out = d_out.cpu().numpy().view(np.uint64).copy()
@@ -474,6 +525,7 @@ def main():
         pa.pa_destroy(ctx)
         return
     if not args.no_extra:
+        progress("extras: n1e6, n1e7, host-to-host, cached multiplier, Toeplitz, batch, served")
         b6 = workloads.single("n1e6")
         ms6, _, _ = time_single(pa, ctx, torch, b6, 200, 500)
         extra["n1e6"] = {"ms_per_block": round(ms6, 4), "mbps": round(b6.n / (ms6 * 1e-3) / 1e6, 1),
@@ -490,12 +542,15 @@ def main():
             "n1e6": toeplitz_rate(pa, ctx, torch, workloads.single("n1e6"), 50),
             "n1e8": toeplitz_rate(pa, ctx, torch, blk, 5)}
         extra["batched"] = batched_vs_plain(pa, ctx, torch, workloads)
+        progress("batch done")
         extra["served"] = served(pa, torch, workloads, args.served_requests)
+        progress("served done")
 
     cpu = None
     bit_exact = None
     if not args.no_cpu:
-        want, cpu = cpu_baseline(blk, key, args.cpu_single_thread)
+        progress("CPU oracle")
+        want, cpu = cpu_baseline(blk, key, not args.no_cpu_single_thread)
         bit_exact = bool(np.array_equal(gpu_out, want))
 
     plan = pa.pa_plan_get(ctx, blk.n)

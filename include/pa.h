@@ -51,6 +51,7 @@ enum pa_status {
     PA_ENOMEM = 2,   /* host or device allocation failed */
     PA_EDEVICE = 3,  /* a HIP runtime call failed (see pa_last_error) */
     PA_ENODEV = 4,   /* no usable gfx950 device with that index */
+    PA_EIO = 5,      /* the tuning cache file could not be read or written */
 };
 
 /* Largest block: 2^23 64-bit digits (transform length 2^24; the coefficient
@@ -59,8 +60,36 @@ enum pa_status {
 
 typedef struct pa_ctx pa_ctx;
 
+/*
+ * Context options (pa_init; NULL gives the defaults: no budget, no cache).
+ *   hbm_budget: the device bytes the context may hold for itself: its twiddle
+ *     tables (0.8 MB), the block workspace (pa_workspace_bytes of the largest
+ *     block so far), the host-transfer staging buffers, the Toeplitz t buffer
+ *     and pa_tune's two temporary buffers.  A call that would grow them past
+ *     it fails with PA_ENOMEM before allocating and leaves the context usable.
+ *     0: no limit.  Batches (pa_batch_bytes), cached multipliers and servers
+ *     are objects of their own, outside it.
+ *   tune_cache: path of a text file of tuned geometries.  pa_init applies the
+ *     file's entries for this GPU architecture (as pa_plan_set would; a
+ *     missing file is an empty cache, an unreadable one PA_EIO), and every
+ *     pa_tune appends its result as one line
+ *       pa_tune <arch> <W> <f> <k> <tile_log> <strided_tile_log> <rows3_log> <ms>
+ *     (digit words W, transform length f 2^k).  Later lines override earlier
+ *     ones; lines of another architecture or format, or whose geometry is not
+ *     valid for the length, are ignored.  NULL: no file.  The matching of the
+ *     multiplication method to the operand size that the paper leaves to GMP
+ *     (Sections 2.3 and 3.2.2) is this measurement, kept across processes.
+ */
+typedef struct pa_opts {
+    uint64_t hbm_budget;
+    const char *tune_cache;
+} pa_opts;
+
 /* Create a context on HIP device `device` (its own stream and tables). */
-int pa_init(pa_ctx **ctx, int device);
+int pa_init(pa_ctx **ctx, int device, const pa_opts *opts);
+
+/* Device bytes the context holds now (what hbm_budget bounds). */
+uint64_t pa_ctx_bytes(const pa_ctx *ctx);
 
 /* Wait for the device (work queued on any stream, including callers' streams
  * through the _async calls), then release the context and everything it owns.
@@ -90,8 +119,10 @@ int pa_hash_ex(pa_ctx *ctx, const uint64_t *key, const uint64_t *c, const uint64
                uint64_t n, uint64_t m, uint64_t *out);
 
 /*
- * Asynchronous, device memory: d_key (ceil(n/64) words) and d_out (ceil(m/64)
- * words) are device pointers; the work is queued on `stream` (a hipStream_t,
+ * Asynchronous, device memory: the same g_{c,d} (Section 2.3, eq. (6) and the
+ * definition after it; the steps of Section 3.2) with c and d expanded from
+ * the seeds.  d_key (ceil(n/64) words) and d_out (ceil(m/64) words) are
+ * device pointers; the work is queued on `stream` (a hipStream_t,
  * NULL for the null stream) and the call returns without waiting.  The
  * context's workspace is reused by every call, so calls on one context must
  * be ordered (one stream, or the caller synchronises between streams).  The
@@ -137,7 +168,6 @@ int pa_hash_async_noalloc(pa_ctx *ctx, const uint64_t *d_key, uint64_t seed_a, u
 enum pa_kernel_kind {
     PA_K_NTT_PASS = 0,    /* one LDS pass of a forward, fused or inverse NTT */
     PA_K_CARRY_LOCAL = 1, /* CRT + addend + column sums -> carry function per chunk */
-    PA_K_CARRY_SCAN = 2,  /* reserved: each apply workgroup now forms its chunk's carry-in itself */
     PA_K_CARRY_APPLY = 3, /* carry-in from the chunk functions, CRT + addend + resolve + mod 2^n + top-m */
 };
 typedef struct pa_profile {
@@ -259,8 +289,11 @@ size_t pa_batch_launches(const pa_batch *batch);
 
 void pa_batch_destroy(pa_batch *batch);
 
-/* create (grouped) + run + wait + pa_batch_result + destroy; per-block
- * status in jobs[i].status. */
+/* g_{c,d} (Section 2.3, eq. (6) and the definition after it; the steps of
+ * Section 3.2) of every block of `jobs`: create (grouped) + run + wait +
+ * pa_batch_result + destroy; per-block status in jobs[i].status.  Returns
+ * PA_OK if every valid block was hashed (invalid ones only get their status),
+ * else the first failure's code. */
 int pa_hash_many(pa_ctx *ctx, pa_job *jobs, size_t count, void *stream);
 
 /*
@@ -297,9 +330,21 @@ int pa_server_create(int device, const pa_server_opts *opts, pa_server **server)
 
 /* Queue one request.  Host pointers by default: key (ceil(n/64) words) must
  * stay valid and out (ceil(m/64) words) untouched until the request is done.
- * With PA_SUBMIT_DEVICE both are device pointers.  *ticket identifies it. */
+ * With PA_SUBMIT_DEVICE both are device pointers, and the server's streams do
+ * not wait for the caller's: the key and out must be complete (written, and
+ * no longer read or written by queued work) when the call is made.
+ * *ticket identifies it. */
 int pa_server_submit(pa_server *s, const uint64_t *key, uint64_t seed_a, uint64_t seed_b,
                      uint64_t n, uint64_t m, uint64_t *out, int flags, uint64_t *ticket);
+
+/* The same for a device request whose key or out are still being produced by
+ * queued work: `ready` (a hipEvent_t recorded after that work) is waited on by
+ * the request's stream before its first kernel.  The event must stay valid
+ * until the request is done.  NULL behaves as pa_server_submit; a non-NULL
+ * event without PA_SUBMIT_DEVICE is PA_EINVAL. */
+int pa_server_submit_after(pa_server *s, const uint64_t *key, uint64_t seed_a, uint64_t seed_b,
+                           uint64_t n, uint64_t m, uint64_t *out, int flags, void *ready,
+                           uint64_t *ticket);
 
 /* Block until the request is done; its status and submit-to-result latency.
  * The ticket is then retired: a second wait on it returns PA_EINVAL.  Tickets
@@ -374,8 +419,12 @@ int pa_plan_set(pa_ctx *ctx, uint64_t n, const pa_plan *p);
  */
 int pa_tune(pa_ctx *ctx, uint64_t n, int reps, pa_plan *best);
 
-/* Transform length used for a block of n bits: the smallest 2^k (k >= 6) or
- * 3 * 2^k (k >= 16) that is >= 2 ceil(n/32) - 1. */
+/* Transform length used for a block of n bits (0 for n == 0 or n > PA_MAX_N).
+ * The block takes the digit layout with less transform work (primes x L x
+ * log2 L): W = 2 (64-bit digits, five primes) or W = 3 (96-bit digits, seven
+ * primes, only for lengths that divide 3 * 2^22).  For D = ceil(n / (32 W))
+ * digits, L is the smallest 2^k (k >= 6) or, when 3 * 2^(k-2) >= 2^18, the
+ * smaller 3 * 2^(k-2), that is >= 2 D - 1 (a linear convolution's length). */
 uint64_t pa_transform_length(uint64_t n);
 
 /*

@@ -28,12 +28,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpa.so")
 
-PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENODEV = 0, 1, 2, 3, 4
+PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENODEV, PA_EIO = 0, 1, 2, 3, 4, 5
 PA_MAX_N = 1 << 29
 PA_TOEPLITZ_MAX_M = 3 << 24
 PA_PROFILE_MAX = 32
 PA_NOALLOC_MAX_BYTES = 120 << 20
-KERNEL_KINDS = {0: "ntt_pass", 1: "carry_local", 2: "carry_scan (reserved)", 3: "carry_apply"}
+KERNEL_KINDS = {0: "ntt_pass", 1: "carry_local", 3: "carry_apply"}
 
 
 class PAError(RuntimeError):
@@ -93,8 +93,14 @@ import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 
+class _Opts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("tune_cache", ctypes.c_char_p)]
+
+
 _lib.pa_init.restype = ctypes.c_int
-_lib.pa_init.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+_lib.pa_init.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(_Opts)]
+_lib.pa_ctx_bytes.restype = ctypes.c_uint64
+_lib.pa_ctx_bytes.argtypes = [ctypes.c_void_p]
 _lib.pa_destroy.restype = None
 _lib.pa_destroy.argtypes = [ctypes.c_void_p]
 _lib.pa_strerror.restype = ctypes.c_char_p
@@ -170,6 +176,10 @@ _lib.pa_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(_ServerOpts),
 _lib.pa_server_submit.restype = ctypes.c_int
 _lib.pa_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _u64, _u64, _u64, _u64,
                                   ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+_lib.pa_server_submit_after.restype = ctypes.c_int
+_lib.pa_server_submit_after.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _u64, _u64, _u64, _u64,
+                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_uint64)]
 _lib.pa_server_wait.restype = ctypes.c_int
 _lib.pa_server_wait.argtypes = [ctypes.c_void_p, _u64, ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_double)]
@@ -229,10 +239,17 @@ def _stream_handle(stream) -> int | None:
     return getattr(stream, "cuda_stream", stream)
 
 
-def pa_init(device: int = 0):
+def pa_init(device: int = 0, hbm_budget: int = 0, tune_cache: str | None = None):
+    """A context on `device`; hbm_budget bounds the device bytes it holds (0:
+    none), tune_cache names the file of tuned geometries (None: no file)."""
     ctx = ctypes.c_void_p()
-    _check(None, _lib.pa_init(ctypes.byref(ctx), int(device)))
+    opts = _Opts(int(hbm_budget), tune_cache.encode() if tune_cache else None)
+    _check(None, _lib.pa_init(ctypes.byref(ctx), int(device), ctypes.byref(opts)))
     return ctx
+
+
+def pa_ctx_bytes(ctx) -> int:
+    return int(_lib.pa_ctx_bytes(ctx))
 
 
 def pa_destroy(ctx) -> None:
@@ -479,22 +496,29 @@ class Server:
         self.h = h
         self._keep = {}
 
-    def submit(self, key, seed_a: int, seed_b: int, n: int, m: int, out) -> int:
-        """key/out: device tensors (PA_SUBMIT_DEVICE) or host numpy uint64 arrays."""
+    def submit(self, key, seed_a: int, seed_b: int, n: int, m: int, out, ready=None) -> int:
+        """key/out: device tensors (PA_SUBMIT_DEVICE) or host numpy uint64 arrays.
+        ready: for device tensors still being written by queued work, a
+        torch.cuda.Event recorded after that work (kept until the request ends)."""
         t = ctypes.c_uint64()
+        ev = None
         if getattr(key, "is_cuda", False):
             kp, op, flags = _dev_ptr(key, words(n), "key"), _dev_ptr(out, words(m), "out"), 1
+            if ready is not None:
+                ev = getattr(ready, "cuda_event", ready)
         else:
+            if ready is not None:
+                raise ValueError("ready events apply to device requests only")
             if not (isinstance(out, np.ndarray) and out.dtype == np.uint64
                     and out.flags.c_contiguous and out.size >= words(m)):
                 raise ValueError("out: need a contiguous uint64 array of ceil(m/64) words")
             key = _host_words(key, words(n), "key")
             kp, op, flags = key.ctypes.data, out.ctypes.data, 0
-        rc = _lib.pa_server_submit(self.h, kp, seed_a & MASK64, seed_b & MASK64, n, m, op, flags,
-                                   ctypes.byref(t))
+        rc = _lib.pa_server_submit_after(self.h, kp, seed_a & MASK64, seed_b & MASK64, n, m, op,
+                                         flags, ev, ctypes.byref(t))
         if rc != PA_OK:
             raise PAError(rc, pa_strerror(rc))
-        self._keep[t.value] = (key, out)
+        self._keep[t.value] = (key, out, ready)
         return t.value
 
     def wait(self, ticket: int) -> tuple[int, float]:
@@ -515,16 +539,33 @@ class Server:
         return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
 
     def run_trace(self, jobs, arrival_s, device: bool = True):
-        """Open-loop replay: jobs[i] (dicts as for Batch) submitted at
-        arrival_s[i] seconds; returns (latencies_ms, statuses)."""
-        arr = _job_array(jobs) if device else None
-        if not device:
-            raise ValueError("run_trace replays device-resident requests")
+        """Open-loop replay: jobs[i] submitted at arrival_s[i] seconds; returns
+        (latencies_ms, statuses).  device=True: dicts as for Batch (device
+        tensors, complete before the call); device=False: key and out are host
+        numpy uint64 arrays, so every latency includes the key's copy to the
+        device and the result's copy back."""
         k = len(jobs)
+        keep = []                       # host copies that must outlive the call
+        if device:
+            arr = _job_array(jobs)
+        else:
+            arr = (_Job * k)()
+            for i, j in enumerate(jobs):
+                n, m = int(j["n"]), int(j["m"])
+                key = _host_words(j["key"], words(n), "key")
+                keep.append(key)
+                out = j["out"]
+                if not (isinstance(out, np.ndarray) and out.dtype == np.uint64
+                        and out.flags.c_contiguous and out.size >= words(m)):
+                    raise ValueError("out: need a contiguous uint64 array of ceil(m/64) words")
+                arr[i].key, arr[i].out = key.ctypes.data, out.ctypes.data
+                arr[i].seed_a = int(j.get("seed_a", 0)) & MASK64
+                arr[i].seed_b = int(j.get("seed_b", 0)) & MASK64
+                arr[i].n, arr[i].m = n, m
         t = (ctypes.c_double * k)(*[float(x) for x in arrival_s])
         lat = (ctypes.c_double * k)()
         st = (ctypes.c_int * k)()
-        rc = _lib.pa_server_run_trace(self.h, arr, t, k, PA_SUBMIT_DEVICE, lat, st)
+        rc = _lib.pa_server_run_trace(self.h, arr, t, k, PA_SUBMIT_DEVICE if device else 0, lat, st)
         if rc != PA_OK:
             raise PAError(rc, pa_strerror(rc))
         return list(lat), list(st)
@@ -551,8 +592,8 @@ class Server:
 class Context:
     """Owns one pa_ctx; a convenience wrapper over the functions above."""
 
-    def __init__(self, device: int = 0):
-        self.ctx = pa_init(device)
+    def __init__(self, device: int = 0, hbm_budget: int = 0, tune_cache: str | None = None):
+        self.ctx = pa_init(device, hbm_budget, tune_cache)
 
     def close(self):
         if self.ctx:

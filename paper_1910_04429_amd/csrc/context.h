@@ -42,6 +42,12 @@ struct pa_ctx {
     hipEvent_t ev[2 * PA_PROFILE_MAX] = {};
     bool have_events = false;
     char err[512] = {0};
+    // pa_opts: the device bytes the context may hold for itself (0: no limit)
+    // and what it holds now; the file of tuned geometries ("" for none)
+    uint64_t budget = 0;
+    uint64_t held = 0;
+    char tune_cache[1024] = {0};
+    char arch[64] = {0};
 };
 
 namespace pa {

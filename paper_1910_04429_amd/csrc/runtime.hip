@@ -50,6 +50,19 @@ int fail(pa_ctx* ctx, int code, const char* what, hipError_t e = hipSuccess)
         if (e_ != hipSuccess) return fail((ctx), PA_EDEVICE, #call, e_);         \
     } while (0)
 
+// The context's HBM budget: may it replace `freed` bytes it holds by `added`?
+int budget_check(pa_ctx* ctx, uint64_t freed, uint64_t added, const char* what)
+{
+    if (ctx->budget && ctx->held - freed + added > ctx->budget) {
+        snprintf(ctx->err, sizeof ctx->err,
+                 "%s: %llu device bytes would exceed the context's budget of %llu (holding %llu)",
+                 what, (unsigned long long)added, (unsigned long long)ctx->budget,
+                 (unsigned long long)(ctx->held - freed));
+        return PA_ENOMEM;
+    }
+    return PA_OK;
+}
+
 uint64_t words_of(uint64_t bits) { return (bits + 63) / 64; }
 uint64_t digits_of(uint64_t bits) { return (bits + 31) / 32; }
 // Transform elements of an n-bit operand cut into digits of W 32-bit words.
@@ -201,11 +214,17 @@ int plan_steps(int r, int* st, bool strided)
     return n;
 }
 
+uint64_t workspace_bytes_of(uint64_t elems, uint64_t D)
+{
+    return elems ? 2 * elems * 4 + std::max<uint64_t>(status_words(D), 1) * 4 : 0;
+}
+
 void free_workspace(pa_ctx* ctx)
 {
     (void)hipFree(ctx->A);
     (void)hipFree(ctx->B);
     (void)hipFree(ctx->status);
+    ctx->held -= workspace_bytes_of(ctx->cap_L, ctx->cap_D);
     ctx->A = ctx->B = ctx->status = nullptr;
     ctx->cap_L = ctx->cap_D = 0;
 }
@@ -218,6 +237,9 @@ int ensure_caps(pa_ctx* ctx, uint64_t elems, uint64_t D)
         return PA_OK;
     elems = std::max(elems, ctx->cap_L);
     D = std::max(D, ctx->cap_D);
+    int rc = budget_check(ctx, workspace_bytes_of(ctx->cap_L, ctx->cap_D),
+                          workspace_bytes_of(elems, D), "workspace");
+    if (rc) return rc;
     PA_HIP(ctx, hipDeviceSynchronize());
     free_workspace(ctx);
     hipError_t e = hipSuccess;
@@ -229,6 +251,7 @@ int ensure_caps(pa_ctx* ctx, uint64_t elems, uint64_t D)
     }
     ctx->cap_L = elems;
     ctx->cap_D = D;
+    ctx->held += workspace_bytes_of(elems, D);
     return PA_OK;
 }
 
@@ -238,7 +261,13 @@ int ensure_staging(pa_ctx* ctx, uint64_t words, bool operands)
 {
     if (words <= ctx->cap_words && (!operands || ctx->d_c))
         return PA_OK;
+    // operand buffers, once made, are kept when the buffers grow
+    const bool ops = operands || ctx->d_c != nullptr;
     const uint64_t w = words > ctx->cap_words ? words : ctx->cap_words;
+    const uint64_t old_bytes = ctx->cap_words * 8 * (ctx->d_c ? 4 : 2);
+    const uint64_t new_bytes = w * 8 * (ops ? 4 : 2);
+    int rc = budget_check(ctx, old_bytes, new_bytes, "staging buffers");
+    if (rc) return rc;
     if (ctx->cap_words) PA_HIP(ctx, hipDeviceSynchronize());   // nothing may still use them
     (void)hipFree(ctx->d_key);
     (void)hipFree(ctx->d_out);
@@ -246,14 +275,21 @@ int ensure_staging(pa_ctx* ctx, uint64_t words, bool operands)
     (void)hipFree(ctx->d_d);
     ctx->d_key = ctx->d_out = ctx->d_c = ctx->d_d = nullptr;
     ctx->cap_words = 0;
+    ctx->held -= old_bytes;
     hipError_t e = hipSuccess;
     if ((e = hipMalloc(&ctx->d_key, w * 8)) != hipSuccess ||
         (e = hipMalloc(&ctx->d_out, w * 8)) != hipSuccess ||
-        (operands && (e = hipMalloc(&ctx->d_c, w * 8)) != hipSuccess) ||
-        (operands && (e = hipMalloc(&ctx->d_d, w * 8)) != hipSuccess)) {
+        (ops && (e = hipMalloc(&ctx->d_c, w * 8)) != hipSuccess) ||
+        (ops && (e = hipMalloc(&ctx->d_d, w * 8)) != hipSuccess)) {
+        (void)hipFree(ctx->d_key);
+        (void)hipFree(ctx->d_out);
+        (void)hipFree(ctx->d_c);
+        (void)hipFree(ctx->d_d);
+        ctx->d_key = ctx->d_out = ctx->d_c = ctx->d_d = nullptr;
         return fail(ctx, PA_ENOMEM, "staging allocation", e);
     }
     ctx->cap_words = w;
+    ctx->held += new_bytes;
     return PA_OK;
 }
 
@@ -985,13 +1021,17 @@ int seeded_t(pa_ctx* ctx, uint64_t seed_t, uint64_t bits, hipStream_t stream, co
 {
     const uint64_t w = words_of(bits);
     if (w > ctx->cap_tbits) {
+        int rc = budget_check(ctx, ctx->cap_tbits * 8, w * 8, "Toeplitz t buffer");
+        if (rc) return rc;
         PA_HIP(ctx, hipDeviceSynchronize());
         (void)hipFree(ctx->tbits);
+        ctx->held -= ctx->cap_tbits * 8;
         ctx->tbits = nullptr;
         ctx->cap_tbits = 0;
         hipError_t e = hipMalloc(&ctx->tbits, w * 8);
         if (e != hipSuccess) return fail(ctx, PA_ENOMEM, "Toeplitz t allocation", e);
         ctx->cap_tbits = w;
+        ctx->held += w * 8;
     }
     PA_HIP(ctx, launch_stream_words(seed_t, w, ctx->tbits, stream));
     *t = ctx->tbits;
@@ -1070,6 +1110,46 @@ int candidates(Len len, pa_plan* out, int max)
     return n;
 }
 
+// The tuning cache: one line per tuned transform length,
+//   pa_tune <arch> <W> <f> <k> <t> <ts> <r0> <ms>
+// (digit words, L = f 2^k, the geometry, the measured time of one hash).
+// Later lines override earlier ones; lines for another architecture, of
+// another format or with a geometry invalid for their length are ignored.
+bool append_tuned(const char* path, const char* arch, Len len, int t, int ts, int r0, float ms)
+{
+    FILE* f = fopen(path, "a");
+    if (!f) return false;
+    const int ok = fprintf(f, "pa_tune %s %d %d %d %d %d %d %.6f\n", arch, len.W, len.f, len.k, t,
+                           ts, r0, (double)ms);
+    return fclose(f) == 0 && ok > 0;
+}
+
+// Load the cache into ctx->plans; a missing file is an empty cache.
+int load_tuned(pa_ctx* ctx)
+{
+    FILE* f = fopen(ctx->tune_cache, "r");
+    if (!f) return PA_OK;
+    char line[256], arch[64];
+    while (fgets(line, sizeof line, f)) {
+        int W = 0, fct = 0, k = 0, t = 0, ts = 0, r0 = 0;
+        float ms = 0.f;
+        if (sscanf(line, "pa_tune %63s %d %d %d %d %d %d %f", arch, &W, &fct, &k, &t, &ts, &r0, &ms) != 8)
+            continue;
+        if (strcmp(arch, ctx->arch) != 0 || (W != 2 && W != 3) || (fct != 1 && fct != 3) || k < 6 ||
+            k > kLogMaxLen)
+            continue;
+        Len len{fct, k};
+        len.W = W;
+        Plan pl;
+        if (!make_plan(len, &pl, 1, PlanParams{t, ts, r0})) continue;
+        const int slot = len_slot(len);
+        if (slot < pa_ctx::kPlanSlots) ctx->plans[slot] = pa_ctx::PlanChoice{t, ts, r0};
+    }
+    const bool bad = ferror(f);
+    fclose(f);
+    return bad ? fail(ctx, PA_EIO, "reading the tuning cache file") : PA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1082,6 +1162,7 @@ const char* pa_strerror(int status)
     case PA_ENOMEM: return "out of memory";
     case PA_EDEVICE: return "device error";
     case PA_ENODEV: return "no usable gfx950 device";
+    case PA_EIO: return "tuning cache file error";
     default: return "unknown status";
     }
 }
@@ -1094,6 +1175,8 @@ uint64_t pa_transform_length(uint64_t n)
     return len_of(n);
 }
 
+uint64_t pa_ctx_bytes(const pa_ctx* ctx) { return ctx ? ctx->held : 0; }
+
 uint64_t pa_workspace_bytes(uint64_t n)
 {
     if (n == 0 || n > PA_MAX_N) return 0;
@@ -1101,10 +1184,12 @@ uint64_t pa_workspace_bytes(uint64_t n)
     return 2 * arr_elems(n) * 4 + status_words(D) * 4;
 }
 
-int pa_init(pa_ctx** out, int device)
+int pa_init(pa_ctx** out, int device, const pa_opts* opts)
 {
     if (!out) return PA_EINVAL;
     *out = nullptr;
+    if (opts && opts->tune_cache && strlen(opts->tune_cache) >= sizeof(((pa_ctx*)nullptr)->tune_cache))
+        return PA_EINVAL;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
         return PA_ENODEV;
@@ -1115,6 +1200,12 @@ int pa_init(pa_ctx** out, int device)
     pa_ctx* ctx = new (std::nothrow) pa_ctx;
     if (!ctx) return PA_ENOMEM;
     ctx->device = device;
+    snprintf(ctx->arch, sizeof ctx->arch, "%s", prop.gcnArchName);
+    if (char* colon = strchr(ctx->arch, ':')) *colon = 0;   // drop feature suffixes
+    if (opts) {
+        ctx->budget = opts->hbm_budget;
+        if (opts->tune_cache) snprintf(ctx->tune_cache, sizeof ctx->tune_cache, "%s", opts->tune_cache);
+    }
     int rc = PA_OK;
     uint32_t *h_lo = nullptr, *h_hi = nullptr;
     do {
@@ -1131,6 +1222,8 @@ int pa_init(pa_ctx** out, int device)
             rc = PA_EDEVICE;
             break;
         }
+        const uint64_t table_bytes = sizeof(uint32_t) * kNumPrimes * (4096 + kRootHi);
+        if ((rc = budget_check(ctx, 0, table_bytes, "twiddle tables")) != PA_OK) break;
         h_lo = new (std::nothrow) uint32_t[kNumPrimes * 4096];
         h_hi = new (std::nothrow) uint32_t[kNumPrimes * kRootHi];
         if (!h_lo || !h_hi) { rc = PA_ENOMEM; break; }
@@ -1155,6 +1248,7 @@ int pa_init(pa_ctx** out, int device)
             rc = PA_ENOMEM;
             break;
         }
+        ctx->held += table_bytes;
         if (hipMemcpy(ctx->pass_lo, h_lo, sizeof(uint32_t) * kNumPrimes * 4096,
                       hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(ctx->pass_hi, h_hi, sizeof(uint32_t) * kNumPrimes * kRootHi,
@@ -1163,6 +1257,7 @@ int pa_init(pa_ctx** out, int device)
             break;
         }
         rc = scratch_address(ctx, device, &ctx->scratch);
+        if (rc == PA_OK && ctx->tune_cache[0]) rc = load_tuned(ctx);
     } while (0);
     delete[] h_lo;
     delete[] h_hi;
@@ -1754,6 +1849,8 @@ int pa_tune(pa_ctx* ctx, uint64_t n, int reps, pa_plan* best)
     const int nc = candidates(len, cand, 64);
     if (nc == 0) return fail(ctx, PA_EINVAL, "internal: no plan");
     const uint64_t m = std::max<uint64_t>(1, n / 2);
+    rc = budget_check(ctx, 0, (words_of(n) + words_of(m)) * 8, "tuning buffers");
+    if (rc) return rc;
     uint64_t *d_key = nullptr, *d_out = nullptr;
     hipError_t e = hipMalloc(&d_key, words_of(n) * 8);
     if (e == hipSuccess) e = hipMalloc(&d_out, words_of(m) * 8);
@@ -1829,6 +1926,11 @@ int pa_tune(pa_ctx* ctx, uint64_t n, int reps, pa_plan* best)
                                               : cand[best_i].tile_log,
                                           cand[best_i].rows3_log};
     if (best) *best = cand[best_i];
+    if (ctx->tune_cache[0]) {
+        const auto& pc = ctx->plans[slot];
+        if (!append_tuned(ctx->tune_cache, ctx->arch, len, pc.t, pc.ts, pc.r0, best_ms))
+            return fail(ctx, PA_EIO, "pa_tune: cannot append to the tuning cache file");
+    }
     return PA_OK;
 }
 

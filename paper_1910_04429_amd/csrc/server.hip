@@ -39,6 +39,7 @@ struct Request {
     uint64_t* out = nullptr;
     uint64_t seed_a = 0, seed_b = 0, n = 0, m = 0;
     bool device = false;          // key/out are device pointers
+    hipEvent_t ready = nullptr;   // device requests: wait for it before the first kernel
     Clock::time_point submitted, finished;
     int status = -1;              // -1 pending/running, else a PA_* code
     bool done = false;
@@ -113,6 +114,9 @@ int start(pa_server* s, Slot& sl, Request* r, uint64_t off, uint64_t bytes)
             return PA_EDEVICE;
         dkey = kbuf;
     }
+    // a device request's key (and out) may still be written by the caller's
+    // work: the slot's stream waits for the event the caller gave
+    if (r->ready && hipStreamWaitEvent(sl.stream, r->ready, 0) != hipSuccess) return PA_EDEVICE;
     b.key = reinterpret_cast<const uint32_t*>(dkey);
     b.seed_a = r->seed_a;
     b.seed_b = r->seed_b;
@@ -255,7 +259,7 @@ int pa_server_create(int device, const pa_server_opts* opts, pa_server** out)
     pa_server* s = new (std::nothrow) pa_server;
     if (!s) return PA_ENOMEM;
     s->opts = *opts;
-    int rc = pa_init(&s->ctx, device);
+    int rc = pa_init(&s->ctx, device, nullptr);
     if (rc) {
         delete s;
         return rc;
@@ -293,10 +297,19 @@ int pa_server_create(int device, const pa_server_opts* opts, pa_server** out)
 int pa_server_submit(pa_server* s, const uint64_t* key, uint64_t seed_a, uint64_t seed_b,
                      uint64_t n, uint64_t m, uint64_t* out, int flags, uint64_t* ticket)
 {
+    return pa_server_submit_after(s, key, seed_a, seed_b, n, m, out, flags, nullptr, ticket);
+}
+
+int pa_server_submit_after(pa_server* s, const uint64_t* key, uint64_t seed_a, uint64_t seed_b,
+                           uint64_t n, uint64_t m, uint64_t* out, int flags, void* ready,
+                           uint64_t* ticket)
+{
     if (!s || !key || !out || !ticket || n == 0 || m == 0 || m > n) return PA_EINVAL;
     if (n > s->opts.max_n) return PA_EINVAL;
+    if (ready && !(flags & PA_SUBMIT_DEVICE)) return PA_EINVAL;
     Request* r = new (std::nothrow) Request;
     if (!r) return PA_ENOMEM;
+    r->ready = (hipEvent_t)ready;
     r->key = key;
     r->out = out;
     r->seed_a = seed_a;

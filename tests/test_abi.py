@@ -46,6 +46,7 @@ def test_host_helpers():
     assert pa.pa_transform_length(0) == 0
     assert pa.pa_workspace_bytes(100_000_000) >= 2 * 7 * 4 * (1 << 21)
     assert pa.pa_strerror(pa.PA_EINVAL) == "invalid argument"
+    assert pa.pa_strerror(pa.PA_EIO) == "tuning cache file error"
 
 
 def test_noalloc_scratch_holds_every_block_up_to_3_2_25_bits():

@@ -181,8 +181,10 @@ def test_longest_five_prime_factor3_transform_closed_forms(pa, ctx):
 
 
 def test_maximum_size_closed_forms(pa, ctx):
-    """n = PA_MAX_N (transform length 2^25): closed forms that hold at any size."""
+    """n = PA_MAX_N (64-bit digits, transform length 2^24): closed forms that
+    hold at any size."""
     n = pa.PA_MAX_N
+    assert pa.pa_transform_length(n) == 1 << 24
     m = n // 3 + 5
     mask = (1 << n) - 1
     sa, sb = 1234, 5678

@@ -164,3 +164,70 @@ def test_invalid_geometry_is_rejected(pa, ctx):
             pa.pa_plan_set(ctx, n, bad)
         assert e.value.status == pa.PA_EINVAL
         assert pa.pa_plan_get(ctx, n) == pa.pa_plan_candidates(n)[0]
+
+
+def test_tuning_cache_file_persists_the_geometry(pa, tmp_path):
+    """pa_tune appends its result to the context's tuning cache; a new context
+    with the same file starts with that geometry, ignores foreign or invalid
+    lines, and stays exact."""
+    import torch
+    path = str(tmp_path / "pa_tune.txt")
+    with open(path, "w") as f:
+        f.write("not a tuning line\n")
+        f.write("pa_tune gfx000 2 1 15 10 10 0 1.0\n")      # another architecture
+        f.write("pa_tune gfx950 2 1 15 99 10 0 1.0\n")      # invalid geometry
+    n, m = 1_000_003, 99_999
+    first = pa.pa_init(0, tune_cache=path)
+    try:
+        tuned = pa.pa_tune(first, n, 2)
+    finally:
+        pa.pa_destroy(first)
+    lines = open(path).read().splitlines()
+    assert lines[-1].startswith("pa_tune gfx950 ")
+    second = pa.pa_init(0, tune_cache=path)
+    try:
+        got = pa.pa_plan_get(second, n)
+        for k in ("tile_log", "strided_tile_log", "rows3_log"):
+            assert got[k] == tuned[k], (k, got, tuned)
+        b = workloads.single_block(41, n, m)
+        d_key = torch.from_numpy(b.key().view(np.int64)).cuda()
+        assert np.array_equal(_hash(pa, second, torch, d_key, b),
+                              oracle.pa_hash(b.key(), b.seed_a, b.seed_b, n, m))
+    finally:
+        pa.pa_destroy(second)
+    # a context without the file keeps the default geometry
+    plain = pa.pa_init(0)
+    try:
+        assert pa.pa_plan_get(plain, n) | {"ms": 0.0} == pa.pa_plan_candidates(n)[0]
+    finally:
+        pa.pa_destroy(plain)
+
+
+def test_hbm_budget_bounds_the_context(pa):
+    """A context whose budget holds the workspace of a 10^6-bit block but not
+    of a 10^8-bit one: the large block fails with PA_ENOMEM before anything is
+    allocated, and the context still hashes the small block exactly."""
+    import torch
+    small, large = workloads.single("n1e6"), workloads.single("n1e8")
+    budget = pa.pa_workspace_bytes(small.n) + (16 << 20)
+    assert budget < pa.pa_workspace_bytes(large.n)
+    ctx = pa.pa_init(0, hbm_budget=budget)
+    try:
+        held = pa.pa_ctx_bytes(ctx)
+        d_large = torch.zeros(workloads.words(large.n), dtype=torch.int64, device="cuda")
+        out = torch.zeros(workloads.words(large.m), dtype=torch.int64, device="cuda")
+        with pytest.raises(pa.PAError) as e:
+            pa.pa_hash_async(ctx, d_large, 1, 2, large.n, large.m, out)
+        assert e.value.status == pa.PA_ENOMEM
+        assert "budget" in pa.pa_last_error(ctx)
+        assert pa.pa_ctx_bytes(ctx) == held
+        d_key = torch.from_numpy(small.key().view(np.int64)).cuda()
+        assert np.array_equal(_hash(pa, ctx, torch, d_key, small),
+                              oracle.pa_hash(small.key(), small.seed_a, small.seed_b, small.n,
+                                             small.m))
+        assert pa.pa_ctx_bytes(ctx) <= budget
+    finally:
+        pa.pa_destroy(ctx)
+    with pytest.raises(pa.PAError) as e:
+        pa.pa_init(0, hbm_budget=1024)                 # cannot hold the twiddle tables
+    assert e.value.status == pa.PA_ENOMEM

@@ -25,10 +25,14 @@ def pa():
 
 
 def _jobs(blocks):
+    """Device requests; complete (synchronised) before they are submitted, as
+    pa_server_submit requires of device keys without a ready event."""
     import torch
-    return [{"key": torch.from_numpy(b.key().view(np.int64)).cuda(),
+    jobs = [{"key": torch.from_numpy(b.key().view(np.int64)).cuda(),
              "out": torch.full((workloads.words(b.m),), -1, dtype=torch.int64, device="cuda"),
              "n": b.n, "m": b.m, "seed_a": b.seed_a, "seed_b": b.seed_b} for b in blocks]
+    torch.cuda.synchronize()
+    return jobs
 
 
 def _host(t):
@@ -80,6 +84,53 @@ def test_host_memory_requests(pa):
             assert st == pa.PA_OK and lat >= 0
     for b, k, o in zip(blocks, keys, outs):
         assert np.array_equal(o, oracle.pa_hash(k, b.seed_a, b.seed_b, b.n, b.m))
+
+
+def test_ready_event_orders_a_key_still_being_written(pa):
+    """Device keys produced by queued work on another stream: each request
+    waits for the event recorded after its key's copy, so it hashes the final
+    key (the copy is queued behind a long dummy kernel, so without the wait the
+    server would read the old contents)."""
+    import torch
+    blocks, _ = workloads.served_requests(24, 6, n_lo=1e5, n_hi=2e6)
+    producer = torch.cuda.Stream()
+    src = [torch.from_numpy(b.key().view(np.int64)).pin_memory() for b in blocks]
+    keys = [torch.zeros(workloads.words(b.n), dtype=torch.int64, device="cuda") for b in blocks]
+    outs = [torch.full((workloads.words(b.m),), -1, dtype=torch.int64, device="cuda")
+            for b in blocks]
+    big = torch.ones((2048, 2048), device="cuda")
+    torch.cuda.synchronize()
+    with pa.Server(hbm_budget=1 << 30, slots=4, max_n=2_000_000) as srv:
+        tickets = []
+        with torch.cuda.stream(producer):
+            for b, k, h, o in zip(blocks, keys, src, outs):
+                for _ in range(20):
+                    big = big @ big / 2048.0              # keeps the producer busy
+                k.copy_(h, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(producer)
+                tickets.append(srv.submit(k, b.seed_a, b.seed_b, b.n, b.m, o, ready=ev))
+        for t in tickets:
+            st, _ = srv.wait(t)
+            assert st == pa.PA_OK
+    torch.cuda.synchronize()
+    for b, o in zip(blocks, outs):
+        assert np.array_equal(_host(o), oracle.pa_hash(b.key(), b.seed_a, b.seed_b, b.n, b.m))
+
+
+def test_host_requests_through_run_trace(pa):
+    """Open-loop replay of host-memory requests: every latency includes the
+    key's copy to the device and the result's copy back; results equal the
+    oracle."""
+    blocks, times = workloads.served_requests(25, 16, n_lo=1e4, n_hi=1e6, rate_per_s=5000.0)
+    jobs = [{"key": b.key(), "out": np.zeros(workloads.words(b.m), dtype=np.uint64), "n": b.n,
+             "m": b.m, "seed_a": b.seed_a, "seed_b": b.seed_b} for b in blocks]
+    with pa.Server(hbm_budget=512 << 20, slots=4, max_n=1_000_000) as srv:
+        lat, st = srv.run_trace(jobs, times, device=False)
+    assert st == [pa.PA_OK] * len(blocks)
+    assert all(x > 0 for x in lat)
+    for b, j in zip(blocks, jobs):
+        assert np.array_equal(j["out"], oracle.pa_hash(b.key(), b.seed_a, b.seed_b, b.n, b.m))
 
 
 def test_admission_respects_budget(pa):
