@@ -63,7 +63,7 @@ def kernel_source_hash() -> str:
     committed counter readings are used only while they describe this code."""
     import re
     h = hashlib.sha256()
-    for f in ("ntt.hip", "field.h", "kernels.h", "swizzle.h"):
+    for f in ("ntt.hip", "pass_body.h", "splitmix.h", "field.h", "kernels.h", "swizzle.h"):
         with open(os.path.join(ROOT, "paper_1910_04429_amd", "csrc", f)) as fh:
             text = re.sub(r"//[^\n]*", "", fh.read())
         h.update("\n".join(l.strip() for l in text.splitlines() if l.strip()).encode())

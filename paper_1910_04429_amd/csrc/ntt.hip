@@ -41,11 +41,25 @@ namespace {
 // One kernel per layout: W = 2 (64-bit digits, the first five primes; also the
 // Toeplitz variant's bit sources over prime 0) and W = 3 (96-bit digits, all
 // seven), so that neither carries the other's primes and sources.
-template <int W>
+// Each kind of pass (pass_kind) has its own instance, so a kernel holds only
+// the code of one kind.
+template <int W, int kKind>
 __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
 {
     extern __shared__ uint32_t sm[];          // 4 N bytes
-    pass_tile_any<W>(a, sm, blockIdx.y, TileCoord{blockIdx.x, gridDim.x, blockIdx.z, true});
+    pass_tile_kind<W, kKind>(a, sm, blockIdx.y, TileCoord{blockIdx.x, gridDim.x, blockIdx.z, true});
+}
+
+template <int W>
+void (*pass_kernel(int kind))(PassArgs)
+{
+    switch (kind) {
+    case kKindFirst: return k_pass<W, kKindFirst>;
+    case kKindForward: return k_pass<W, kKindForward>;
+    case kKindFusedFirst: return k_pass<W, kKindFusedFirst>;
+    case kKindFused: return k_pass<W, kKindFused>;
+    default: return k_pass<W, kKindInverse>;
+    }
 }
 
 }  // namespace
@@ -61,7 +75,8 @@ hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch, co
     const bool w3 = a.dwords == 3;
     if (a.primes < 1 || a.primes > (w3 ? 7 : 5)) return hipErrorInvalidValue;
     const unsigned primes = (unsigned)a.primes;
-    auto kernel = w3 ? k_pass<3> : k_pass<2>;
+    const int kind = pass_kind(a);
+    auto kernel = w3 ? pass_kernel<3>(kind) : pass_kernel<2>(kind);
     if (ev.start)
         hipExtLaunchKernelGGL(kernel, dim3(tiles, primes, batch), dim3(threads),
                               sizeof(uint32_t) * N, stream, ev.start, ev.stop, 0, a);

@@ -600,8 +600,11 @@ __device__ __forceinline__ void dispatch_fused_middle(int r, uint32_t* sm, int N
 }
 
 // One pass over the tile of prime PI owned by this workgroup; digit sources
-// have W 32-bit words per digit.
-template <int PI, int W>
+// have W 32-bit words per digit.  kMode is the pass's mode (a.mode) and kSrc
+// whether its input is an operand source rather than a residue array
+// (a.src != kSrcArray): fixed at compile time, so each kernel carries only
+// the code of its own kind of pass.
+template <int PI, int W, int kMode, bool kSrc>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const TileCoord& tc)
 {
     constexpr uint32_t p = PrimeConst<PI>::p;
@@ -630,7 +633,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
     // positions, so those loads coalesce, and the load sweep and its barrier go.
     const int total = a.nsteps + (a.f == 3);
     const bool contig = a.f == 1 && logC == 0 && a.nsteps >= 2;
-    const bool hbm_in = contig && bv.src == kSrcArray && a.mode != kInverse;
+    const bool hbm_in = !kSrc && kMode != kInverse && contig;
     const StepGeo g0 = step_geo(a, 0, col0);
     const int r0 = (int)(a.steps_code & 15u);
     const GlobalIO io{data + blk0, data + blk0,
@@ -643,9 +646,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
     // (Power-of-two rows, a first or last step of radix >= 4; in the 96-bit
     // layout's kernel only: the 64-bit one serves the short, latency-bound
     // blocks, where the larger kernel measured slower than the saved work.)
-    const bool half_in = W == 3 && (bv.src == kSrcDigits || bv.src == kSrcSeed) && a.f == 1 &&
-                         r0 >= 2 && (a.mode != kFused || total >= 2);
-    const bool half_out = W == 3 && a.mode == kInverse && a.limit_to_digits && a.f == 1 && r0 >= 2;
+    const bool half_in = W == 3 && kSrc && (bv.src == kSrcDigits || bv.src == kSrcSeed) &&
+                         a.f == 1 && r0 >= 2 && (kMode != kFused || total >= 2);
+    const bool half_out = W == 3 && kMode == kInverse && a.limit_to_digits && a.f == 1 && r0 >= 2;
 
     // Tile element (row, c) <-> global position blk0 + row S + col0 + c; moved
     // in groups of 4 consecutive columns (C >= 4) or rows (C == 1); quad u
@@ -664,7 +667,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
             pos = blk0 + e;
         }
         uint4 v;
-        if (bv.src == kSrcArray) {
+        if constexpr (!kSrc) {
             v = *reinterpret_cast<const uint4*>(data + pos);
         } else if (bv.src == kSrcBits) {
             v.x = source_bit(bv, pos + 0);
@@ -693,9 +696,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
     }
     __syncthreads();
 
-    if (a.mode == kInverse) {
+    if constexpr (kMode == kInverse) {
         run_pass_steps<true, PI>(a, sm, N, col0, total, 0, half_out);
-    } else if (a.mode == kFused && hbm_in) {
+    } else if (kMode == kFused && hbm_in) {
         // as below, with the first forward step read from HBM and the last
         // inverse step (its inverse) written to HBM
         run_pass_steps<false, PI>(a, sm, N, col0, total - 1, 1);
@@ -705,7 +708,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
         run_pass_steps<true, PI>(a, sm, N, col0, total - 1, 1);
         dispatch_step_io<true, PI>(r0, sm, N, step_geo(a, 0, col0), a.tb, io);
         return;
-    } else if (a.mode == kFused) {
+    } else if (kMode == kFused) {
         // Forward steps but the last, then the last forward step, the
         // pointwise product with the pre-scaled c-hat (same layout) and the
         // first inverse step together in registers, then the other inverse
@@ -762,29 +765,57 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
 // five primes; also the Toeplitz variant's bit sources over prime 0) or W = 3
 // (96-bit digits, all seven).  The body is instantiated once per prime, so
 // that the prime's constants are immediates.
-template <int W>
+template <int W, int kMode, bool kSrc>
 __device__ __forceinline__ void pass_tile_any(const PassArgs& a, uint32_t* sm, uint32_t prime,
                                               const TileCoord& tc)
 {
     if constexpr (W == 3) {
         switch (prime) {
-        case 0: pass_tile<0, W>(a, sm, tc); break;
-        case 1: pass_tile<1, W>(a, sm, tc); break;
-        case 2: pass_tile<2, W>(a, sm, tc); break;
-        case 3: pass_tile<3, W>(a, sm, tc); break;
-        case 4: pass_tile<4, W>(a, sm, tc); break;
-        case 5: pass_tile<5, W>(a, sm, tc); break;
-        default: pass_tile<6, W>(a, sm, tc); break;
+        case 0: pass_tile<0, W, kMode, kSrc>(a, sm, tc); break;
+        case 1: pass_tile<1, W, kMode, kSrc>(a, sm, tc); break;
+        case 2: pass_tile<2, W, kMode, kSrc>(a, sm, tc); break;
+        case 3: pass_tile<3, W, kMode, kSrc>(a, sm, tc); break;
+        case 4: pass_tile<4, W, kMode, kSrc>(a, sm, tc); break;
+        case 5: pass_tile<5, W, kMode, kSrc>(a, sm, tc); break;
+        default: pass_tile<6, W, kMode, kSrc>(a, sm, tc); break;
         }
     } else {
         switch (prime) {
-        case 0: pass_tile<0, W>(a, sm, tc); break;
-        case 1: pass_tile<1, W>(a, sm, tc); break;
-        case 2: pass_tile<2, W>(a, sm, tc); break;
-        case 3: pass_tile<3, W>(a, sm, tc); break;
-        default: pass_tile<4, W>(a, sm, tc); break;
+        case 0: pass_tile<0, W, kMode, kSrc>(a, sm, tc); break;
+        case 1: pass_tile<1, W, kMode, kSrc>(a, sm, tc); break;
+        case 2: pass_tile<2, W, kMode, kSrc>(a, sm, tc); break;
+        case 3: pass_tile<3, W, kMode, kSrc>(a, sm, tc); break;
+        default: pass_tile<4, W, kMode, kSrc>(a, sm, tc); break;
         }
     }
+}
+
+// The kinds of pass a plan has: (mode, operand source), see pass_tile.
+enum PassKind : int {
+    kKindFirst = 0,        // forward, from the operand (its first pass)
+    kKindForward = 1,      // forward, residue array in place
+    kKindFusedFirst = 2,   // fused, from the key (a one-pass transform)
+    kKindFused = 3,        // fused, residue array in place
+    kKindInverse = 4,      // inverse
+    kPassKinds = 5,
+};
+
+__host__ __device__ inline int pass_kind(const PassArgs& a)
+{
+    const bool src = a.src != kSrcArray;
+    if (a.mode == kInverse) return kKindInverse;
+    if (a.mode == kFused) return src ? kKindFusedFirst : kKindFused;
+    return src ? kKindFirst : kKindForward;
+}
+
+template <int W, int kKind>
+__device__ __forceinline__ void pass_tile_kind(const PassArgs& a, uint32_t* sm, uint32_t prime,
+                                               const TileCoord& tc)
+{
+    constexpr int kMode = kKind == kKindInverse ? kInverse
+                        : (kKind == kKindFused || kKind == kKindFusedFirst) ? kFused : kForward;
+    constexpr bool kSrc = kKind == kKindFirst || kKind == kKindFusedFirst;
+    pass_tile_any<W, kMode, kSrc>(a, sm, prime, tc);
 }
 
 }  // namespace

@@ -112,7 +112,14 @@ __device__ __attribute__((noinline)) void run_item(ConstLaunch* Lp, uint32_t x, 
     z = __builtin_amdgcn_readfirstlane(z);
     if (L->kind == kPersistPass) {
         const PassArgs pa = L->pass;
-        pass_tile_any<W>(pa, sm, y, TileCoord{x, L->gx, z, false});
+        const TileCoord tc{x, L->gx, z, false};
+        switch (pass_kind(pa)) {
+        case kKindFirst: pass_tile_kind<W, kKindFirst>(pa, sm, y, tc); break;
+        case kKindForward: pass_tile_kind<W, kKindForward>(pa, sm, y, tc); break;
+        case kKindFusedFirst: pass_tile_kind<W, kKindFusedFirst>(pa, sm, y, tc); break;
+        case kKindFused: pass_tile_kind<W, kKindFused>(pa, sm, y, tc); break;
+        default: pass_tile_kind<W, kKindInverse>(pa, sm, y, tc); break;
+        }
     } else {
         const CarryArgs ca = L->carry;
         auto& sh = *reinterpret_cast<CarryShared<kPer, W>*>(sm);
