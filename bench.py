@@ -352,9 +352,12 @@ def batched_vs_plain(pa, ctx, torch, workloads):
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     res = {"workload": "256 blocks, n log-uniform in [1e5, 1e7], m = round(r n), "
                        "r uniform in [0.05, 0.5], seed 3", "bits": bits}
-    for name, mode in (("grouped", pa.PA_BATCH_GROUPED),):
-        batch = pa.Batch(ctx, jobs, mode=mode)
+    for name, tune in (("grouped", False), ("grouped_tuned", True)):
+        batch = pa.Batch(ctx, jobs, mode=pa.PA_BATCH_GROUPED)
         try:
+            if tune:
+                batch.tune(3)
+                res["tuned_groups"] = batch.groups()
             batch.capture()
             for _ in range(3):
                 batch.run()
@@ -373,6 +376,7 @@ def batched_vs_plain(pa, ctx, torch, workloads):
         finally:
             batch.close()
     res["grouped"]["runs"] = "one launch per pass per length group, groups on 4 streams, captured HIP graph"
+    res["grouped_tuned"]["runs"] = "the same after pa_batch_tune (geometry per length group, measured)"
     res["persistent"] = "not run: the persistent queue kernel is switched off (not yet validated on a GPU)"
     pa.pa_reserve(ctx, max(b.n for b in blocks))
     for b, j in zip(blocks, jobs):

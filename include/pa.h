@@ -419,6 +419,22 @@ int pa_plan_set(pa_ctx *ctx, uint64_t n, const pa_plan *p);
  */
 int pa_tune(pa_ctx *ctx, uint64_t n, int reps, pa_plan *best);
 
+/*
+ * Autotune a grouped batch: for every length group, time reps runs of the
+ * group alone with each candidate geometry of its length (pa_plan_candidates;
+ * two sweeps, the second in reverse order, after about 30 ms of whole-batch
+ * runs so that the clocks have risen) and keep the fastest for that group.
+ * Synchronises the context's stream and drops a recorded graph (call
+ * pa_batch_capture again).  Every geometry computes the same bits.
+ */
+int pa_batch_tune(pa_batch *batch, int reps);
+
+/* The batch's length groups: their number, and group i's transform length,
+ * block count and geometry. */
+size_t pa_batch_groups(const pa_batch *batch);
+int pa_batch_group(const pa_batch *batch, size_t i, uint64_t *length, uint32_t *blocks,
+                   pa_plan *plan);
+
 /* Transform length used for a block of n bits (0 for n == 0 or n > PA_MAX_N).
  * The block takes the digit layout with less transform work (primes x L x
  * log2 L): W = 2 (64-bit digits, five primes) or W = 3 (96-bit digits, seven

@@ -166,6 +166,13 @@ _lib.pa_batch_launches.restype = ctypes.c_size_t
 _lib.pa_batch_launches.argtypes = [ctypes.c_void_p]
 _lib.pa_batch_destroy.restype = None
 _lib.pa_batch_destroy.argtypes = [ctypes.c_void_p]
+_lib.pa_batch_tune.restype = ctypes.c_int
+_lib.pa_batch_tune.argtypes = [ctypes.c_void_p, ctypes.c_int]
+_lib.pa_batch_groups.restype = ctypes.c_size_t
+_lib.pa_batch_groups.argtypes = [ctypes.c_void_p]
+_lib.pa_batch_group.restype = ctypes.c_int
+_lib.pa_batch_group.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64),
+                                ctypes.POINTER(ctypes.c_uint32), ctypes.c_void_p]
 _lib.pa_hash_many.restype = ctypes.c_int
 _lib.pa_hash_many.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Job), ctypes.c_size_t,
                               ctypes.c_void_p]
@@ -462,6 +469,21 @@ class Batch:
 
     def capture(self, stream=None):
         _check(self.ctx, _lib.pa_batch_capture(self.h, _stream_handle(stream)))
+
+    def tune(self, reps: int = 3):
+        """Time every candidate geometry per length group and keep the fastest
+        (drops a captured graph: capture again afterwards)."""
+        _check(self.ctx, _lib.pa_batch_tune(self.h, int(reps)))
+
+    def groups(self) -> list[dict]:
+        """Per length group: transform length, block count and geometry."""
+        out = []
+        for i in range(int(_lib.pa_batch_groups(self.h))):
+            L, cnt, p = ctypes.c_uint64(), ctypes.c_uint32(), _Plan()
+            _check(self.ctx, _lib.pa_batch_group(self.h, i, ctypes.byref(L), ctypes.byref(cnt),
+                                                 ctypes.byref(p)))
+            out.append({"length": L.value, "blocks": cnt.value} | _plan_dict(p))
+        return out
 
     def bytes(self) -> int:
         return int(_lib.pa_batch_bytes(self.h))

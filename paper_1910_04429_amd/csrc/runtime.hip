@@ -1675,6 +1675,99 @@ int pa_batch_run(pa_batch* b, void* stream)
     return enqueue_batch(b, (hipStream_t)stream);
 }
 
+int pa_batch_tune(pa_batch* b, int reps)
+{
+    if (!b) return PA_EINVAL;
+    pa_ctx* ctx = b->ctx;
+    if (b->mode != PA_BATCH_GROUPED)
+        return fail(ctx, PA_EINVAL, "pa_batch_tune: grouped batches only");
+    PA_HIP(ctx, hipSetDevice(ctx->device));
+    reps = std::max(1, std::min(reps, 100));
+    if (!ctx->have_events) {
+        for (auto& e : ctx->ev) PA_HIP(ctx, hipEventCreate(&e));
+        ctx->have_events = true;
+    }
+    const hipStream_t st = ctx->stream;
+    // a recorded graph holds the old geometries
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    // the clocks rise over tens of milliseconds of load: run the whole batch
+    // for about 30 ms first
+    for (int i = 0; i < 8; ++i) {
+        int rc = enqueue_batch(b, st);
+        if (rc) return rc;
+    }
+    PA_HIP(ctx, hipStreamSynchronize(st));
+    for (auto& g : b->groups) {
+        const Len len{g.plan.f, g.plan.k};
+        Len lw = len;
+        lw.W = g.plan.W;
+        pa_plan cand[64];
+        const int nc = candidates(lw, cand, 64);
+        if (nc < 2) continue;
+        Work w;
+        w.jobs = b->d_jobs + g.first;
+        w.batch = g.count;
+        w.chunks = g.chunks;
+        w.per = g.per;
+        // time reps runs of the group alone with geometry pl; two sweeps, the
+        // second in reverse order, each candidate keeping its faster time
+        auto timed = [&](const Plan& pl, float* ms) -> int {
+            PA_HIP(ctx, hipEventRecord(ctx->ev[0], st));
+            for (int r = 0; r < reps; ++r) {
+                int rc = enqueue_plan(ctx, pl, w, st);
+                if (rc) return rc;
+            }
+            PA_HIP(ctx, hipEventRecord(ctx->ev[1], st));
+            PA_HIP(ctx, hipEventSynchronize(ctx->ev[1]));
+            PA_HIP(ctx, hipEventElapsedTime(ms, ctx->ev[0], ctx->ev[1]));
+            return PA_OK;
+        };
+        std::vector<Plan> plans(nc);
+        std::vector<float> best_ms(nc, 0.f);
+        for (int i = 0; i < nc; ++i) {
+            const PlanParams pp{cand[i].tile_log,
+                                cand[i].strided_tile_log ? cand[i].strided_tile_log : cand[i].tile_log,
+                                cand[i].rows3_log};
+            if (!make_plan(lw, &plans[i], g.count, pp)) return fail(ctx, PA_EINVAL, "internal: plan");
+        }
+        for (int sweep = 0; sweep < 2; ++sweep)
+            for (int k = 0; k < nc; ++k) {
+                const int i = sweep ? nc - 1 - k : k;
+                float ms = 0.f;
+                int rc = timed(plans[i], &ms);
+                if (rc) return rc;
+                best_ms[i] = sweep ? std::min(best_ms[i], ms) : ms;
+            }
+        int bi = 0;
+        for (int i = 1; i < nc; ++i)
+            if (best_ms[i] < best_ms[bi]) bi = i;
+        float cur = 0.f;
+        int rc = timed(g.plan, &cur);
+        if (rc) return rc;
+        if (best_ms[bi] < cur) g.plan = plans[bi];
+    }
+    return PA_OK;
+}
+
+size_t pa_batch_groups(const pa_batch* b) { return b ? b->groups.size() : 0; }
+
+int pa_batch_group(const pa_batch* b, size_t i, uint64_t* length, uint32_t* blocks, pa_plan* plan)
+{
+    if (!b || i >= b->groups.size()) return PA_EINVAL;
+    const auto& g = b->groups[i];
+    if (length) *length = g.plan.L;
+    if (blocks) *blocks = g.count;
+    if (plan) describe(g.plan, plan);
+    return PA_OK;
+}
+
 int pa_batch_capture(pa_batch* b, void* stream)
 {
     if (!b) return PA_EINVAL;

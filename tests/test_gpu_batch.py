@@ -231,3 +231,32 @@ def test_large_blocks_and_both_layouts(pa, ctx):
     assert pa.pa_hash_many(ctx, jobs) == [pa.PA_OK] * len(blocks)
     for b, j in zip(blocks, jobs):
         assert np.array_equal(_host(j["out"]), _want(b)), (b.n, b.m)
+
+
+def test_tuned_batch_stays_exact(pa, ctx):
+    """pa_batch_tune picks a geometry per length group; the tuned batch, run
+    eagerly and through a graph captured after tuning, equals the oracle."""
+    import torch
+    blocks = workloads.batch_blocks(31, 24, n_lo=1e5, n_hi=3e6)
+    jobs = _device_jobs(blocks)
+    batch = pa.Batch(ctx, jobs)
+    try:
+        before = batch.groups()
+        batch.tune(2)
+        after = batch.groups()
+        assert [g["length"] for g in after] == [g["length"] for g in before]
+        assert sum(g["blocks"] for g in after) == len(blocks)
+        batch.run()
+        torch.cuda.synchronize()
+        for b, j in zip(blocks, jobs):
+            assert np.array_equal(_host(j["out"]), _want(b)), (b.n, b.m)
+        batch.capture()
+        for j in jobs:
+            j["out"].fill_(-1)
+        torch.cuda.synchronize()
+        batch.run()
+        torch.cuda.synchronize()
+        for b, j in zip(blocks, jobs):
+            assert np.array_equal(_host(j["out"]), _want(b)), (b.n, b.m)
+    finally:
+        batch.close()
