@@ -28,7 +28,7 @@ __device__ __forceinline__ uint32_t addend_digit(const CarryArgs& a, uint32_t t)
         return 0;
     uint32_t v;
     if (a.addend_src == kSrcDigits) {
-        v = a.addend[t];
+        v = *gmem(a.addend + t);
     } else {
         const uint64_t w = splitmix64(a.seed, t >> 1);
         v = (t & 1) ? (uint32_t)(w >> 32) : (uint32_t)w;
@@ -85,21 +85,21 @@ __device__ __forceinline__ int slot(int i)
 // Batch mode: take the block's sizes, addend, state and output from its job.
 __device__ __forceinline__ void bind_job(CarryArgs& a, uint32_t job)
 {
-    const JobDesc& j = a.jobs[job];
-    a.res = j.B;
-    a.num_digits = j.num_digits;
-    a.n = j.n;
-    a.m = j.m;
-    if (j.d) {
+    const auto* j = gmem(a.jobs + job);
+    a.res = j->B;
+    a.num_digits = j->num_digits;
+    a.n = j->n;
+    a.m = j->m;
+    if (j->d) {
         a.addend_src = kSrcDigits;
-        a.addend = j.d;
+        a.addend = j->d;
     } else {
         a.addend_src = kSrcSeed;
-        a.seed = j.seed_b;
+        a.seed = j->seed_b;
     }
-    a.desc = j.carry;
-    a.out = j.out;
-    a.chunks = j.chunks;
+    a.desc = j->carry;
+    a.out = j->out;
+    a.chunks = j->chunks;
 }
 
 // Residues of coefficient K (0 outside [0, ceil(D / W))).
@@ -109,7 +109,7 @@ __device__ __forceinline__ void load_res(const CarryArgs& a, int64_t K, uint32_t
     const int64_t coeffs = (a.num_digits + W - 1) / W;
 #pragma unroll
     for (int pi = 0; pi < 2 * W + 1; ++pi)
-        r[pi] = (K < 0 || K >= coeffs) ? 0u : a.res[(size_t)pi * a.L + K];
+        r[pi] = (K < 0 || K >= coeffs) ? 0u : *gmem(a.res + (size_t)pi * a.L + K);
 }
 
 // Exact coefficient K (0 outside the product's coefficients).
@@ -180,13 +180,13 @@ __device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_
         for (int pi = 0; pi < NP; ++pi) {
             const uint32_t* src = a.res + (size_t)pi * a.L + K0;
             if constexpr (kCo == 2) {
-                const uint2 q = *reinterpret_cast<const uint2*>(src);
+                const u32x2 q = *gmem(reinterpret_cast<const u32x2*>(src));
                 r[pi][0] = q.x;
                 r[pi][1] = q.y;
             } else {
 #pragma unroll
                 for (int v = 0; v < kCo / 4; ++v) {
-                    const uint4 q = reinterpret_cast<const uint4*>(src)[v];
+                    const u32x4 q = *gmem(reinterpret_cast<const u32x4*>(src) + v);
                     r[pi][4 * v] = q.x;
                     r[pi][4 * v + 1] = q.y;
                     r[pi][4 * v + 2] = q.z;
@@ -289,7 +289,7 @@ __device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_
 
     if (!kApply) {
         if (tid == kCarryThreads - 1)
-            a.desc[chunk] = carry_compose(before, f);
+            *gmem(a.desc + chunk) = carry_compose(before, f);
         return;
     }
     // carry entering this chunk: the functions of chunks 0 .. chunk-1 (written
@@ -303,7 +303,7 @@ __device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_
         const uint32_t lo = (uint32_t)tid * per_t;
         uint32_t g = kCarryIdentity;
         for (uint32_t k = lo; k < lo + per_t && k < chunk; ++k)
-            g = carry_compose(g, a.desc[k]);
+            g = carry_compose(g, *gmem(a.desc + k));
         g = wave_scan(g, lane);
         if (lane == 63)
             wpre[wave] = g;
@@ -356,7 +356,7 @@ __device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_
         if (sh) w |= v2 << (64 - sh);
         if (j == words - 1 && (a.m & 63))
             w &= (1ull << (a.m & 63)) - 1ull;
-        a.out[j] = w;
+        *gmem(a.out + j) = w;
     }
 }
 

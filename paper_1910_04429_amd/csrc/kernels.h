@@ -9,6 +9,19 @@
 
 namespace pa {
 
+// Global-memory views of the buffers the kernels read and write.  Loads and
+// stores through them compile to global_* instructions instead of flat_*
+// ones: a flat access also counts against the LDS wait counter, so every wait
+// for an LDS result would also wait for the outstanding HBM accesses.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 constexpr int kTileLog = 14;                 // largest LDS tile: 2^14 residues, 64 KB
 constexpr int kTileMinLog = 10;              // smallest tile of a multi-pass transform
 constexpr int kStridedMaxLog = 9;            // strided passes: <= 512 rows

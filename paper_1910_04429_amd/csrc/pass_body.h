@@ -104,25 +104,25 @@ __device__ __forceinline__ BlockView block_view(const PassArgs& a, uint32_t z)
 {
     BlockView v{a.data, a.other, a.digits, a.seed, a.n, a.bit_off, a.num_digits, a.store_limit, a.src};
     if (a.jobs) {
-        const JobDesc& j = a.jobs[z];
-        v.n = j.n;
-        v.num_digits = j.num_digits;
-        v.data = (a.role == kRoleMul) ? j.A : j.B;
-        v.other = j.A;
+        const auto* j = gmem(a.jobs + z);
+        v.n = j->n;
+        v.num_digits = j->num_digits;
+        v.data = (a.role == kRoleMul) ? j->A : j->B;
+        v.other = j->A;
         if (a.src != kSrcArray) {             // first pass: the operand's digits
             if (a.role == kRoleKey) {
                 v.src = kSrcDigits;
-                v.digits = j.key;
-            } else if (j.c) {
+                v.digits = j->key;
+            } else if (j->c) {
                 v.src = kSrcDigits;
-                v.digits = j.c;
+                v.digits = j->c;
             } else {
                 v.src = kSrcSeed;
-                v.seed = j.seed_a;
+                v.seed = j->seed_a;
             }
         }
         if (a.limit_to_digits)
-            v.store_limit = ((j.num_digits + a.dwords - 1u) / a.dwords + 3u) & ~3u;
+            v.store_limit = ((j->num_digits + a.dwords - 1u) / a.dwords + 3u) & ~3u;
     } else if (a.dual && z == 1) {
         v.data = const_cast<uint32_t*>(a.other);
         v.src = kSrcDigits;
@@ -147,13 +147,13 @@ __device__ __forceinline__ void source_quad(const BlockView& a, uint32_t pos, ui
         if (d0 + 4 * W <= D && (reinterpret_cast<uintptr_t>(a.digits) & 15u) == 0) {
 #pragma unroll
             for (int q = 0; q < W; ++q) {
-                const uint4 t = *reinterpret_cast<const uint4*>(a.digits + d0 + 4 * q);
+                const u32x4 t = *gmem(reinterpret_cast<const u32x4*>(a.digits + d0 + 4 * q));
                 v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 4 * W; ++i)
-                if (d0 + i < D) v[i] = a.digits[d0 + i];
+                if (d0 + i < D) v[i] = *gmem(a.digits + d0 + i);
         }
     } else {
 #pragma unroll
@@ -182,7 +182,7 @@ __device__ __forceinline__ uint32_t source_bit(const BlockView& a, uint32_t t)
     if (t >= a.n)
         return 0;
     const uint64_t b = a.bit_off + t;
-    return (a.digits[b >> 5] >> (b & 31)) & 1u;
+    return (*gmem(a.digits + (b >> 5)) >> (b & 31)) & 1u;
 }
 
 // Montgomery form of w^E for the root w of order kOrder, E < kOrder (for a
@@ -190,8 +190,8 @@ __device__ __forceinline__ uint32_t source_bit(const BlockView& a, uint32_t t)
 template <int PI>
 __device__ __forceinline__ uint32_t root_pow(const Tables& tb, uint32_t E)
 {
-    const uint32_t lo = tb.pass_lo[PI * 4096 + (E & 4095u)];
-    const uint32_t hi = tb.pass_hi[PI * kRootHi + (E >> 12)];
+    const uint32_t lo = *gmem(tb.pass_lo + PI * 4096 + (E & 4095u));
+    const uint32_t hi = *gmem(tb.pass_hi + PI * kRootHi + (E >> 12));
     return fmul_mont(lo, hi, PrimeConst<PI>::p, PrimeConst<PI>::pneg);
 }
 
@@ -333,7 +333,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
                 if (kHalf && n >= RHO / 2)
                     x[n] = 0u;
                 else
-                    x[n] = (kIO == 1) ? io.in[base + n * nstep] : sm[sb ^ swz(n * nstep)];
+                    x[n] = (kIO == 1) ? *gmem(io.in + base + n * nstep) : sm[sb ^ swz(n * nstep)];
             }
             dif_regs<R, PI, kHalf>(x);
             if (twiddle) {
@@ -367,7 +367,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
                 if (kHalf && n >= RHO / 2)
                     continue;
                 if (kIO == 2) {
-                    if (base + n * nstep < io.limit) io.out[base + n * nstep] = x[n];
+                    if (base + n * nstep < io.limit) *gmem(io.out + base + n * nstep) = x[n];
                 } else {
                     sm[sb ^ swz(n * nstep)] = x[n];
                 }
@@ -530,7 +530,7 @@ __device__ __forceinline__ void fused_middle(uint32_t* sm, int N, const uint32_t
         if (RHO >= 4) {
 #pragma unroll
             for (int v = 0; v < RHO / 4; ++v) {
-                const uint4 w = *reinterpret_cast<const uint4*>(chat + base + 4 * v);
+                const u32x4 w = *gmem(reinterpret_cast<const u32x4*>(chat + base + 4 * v));
                 c[4 * v] = w.x;
                 c[4 * v + 1] = w.y;
                 c[4 * v + 2] = w.z;
@@ -538,7 +538,7 @@ __device__ __forceinline__ void fused_middle(uint32_t* sm, int N, const uint32_t
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < RHO; ++k) c[k] = chat[base + k];
+            for (int k = 0; k < RHO; ++k) c[k] = *gmem(chat + base + k);
         }
 #pragma unroll
         for (int k = 0; k < RHO; ++k) {
@@ -582,8 +582,8 @@ __device__ __forceinline__ void last_step_store(const uint32_t* sm, int N, uint3
 #pragma unroll
         for (int v = 0; v < RHO / 4; ++v)
             if (base + 4 * v < limit)
-                *reinterpret_cast<uint4*>(out + base + 4 * v) =
-                    make_uint4(y[4 * v], y[4 * v + 1], y[4 * v + 2], y[4 * v + 3]);
+                *gmem(reinterpret_cast<u32x4*>(out + base + 4 * v)) =
+                    u32x4{y[4 * v], y[4 * v + 1], y[4 * v + 2], y[4 * v + 3]};
     }
 }
 
@@ -668,7 +668,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
         }
         uint4 v;
         if constexpr (!kSrc) {
-            v = *reinterpret_cast<const uint4*>(data + pos);
+            const u32x4 t = *gmem(reinterpret_cast<const u32x4*>(data + pos));
+            v = make_uint4(t.x, t.y, t.z, t.w);
         } else if (bv.src == kSrcBits) {
             v.x = source_bit(bv, pos + 0);
             v.y = source_bit(bv, pos + 1);
@@ -757,7 +758,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
             v.w = fmul_shoup(v.w, w, q, p);
         }
         if (pos < bv.store_limit)
-            *reinterpret_cast<uint4*>(data + pos) = v;
+            *gmem(reinterpret_cast<u32x4*>(data + pos)) = u32x4{v.x, v.y, v.z, v.w};
     }
 }
 
