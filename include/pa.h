@@ -392,7 +392,9 @@ typedef struct pa_plan {
     int strided_tile_log;  /* strided pass tiles, log2 residues (0 with one pass) */
     int rows3_log;         /* lengths 3 * 2^k: log2 of the factor-3 pass rows / 3; else 0 */
     int passes;            /* out: passes per transform */
-    float ms;              /* out (pa_tune): one hash of the tuning block with this plan */
+    float ms;              /* out: pa_tune, one hash of the tuning block with this plan;
+                              pa_batch_group, one run of the group alone after
+                              pa_batch_tune (0 before) */
 } pa_plan;
 
 /* Valid distinct geometries for blocks of n bits (the default first); writes

@@ -22,6 +22,19 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p)
     return (__attribute__((address_space(1))) T*)p;
 }
 
+// Word i of an array whose base is the same for the whole wave, as a V (a
+// word or a vector of words), addressed by the base plus a 32-bit byte offset:
+// the form of global access that takes a scalar base and one vector register
+// per address, where base + i computed in 64 bits takes two vector registers
+// per address (and a 64-bit add), or a scalar-register pair per distinct
+// uniform offset.  The array must be shorter than 2^30 words.
+template <class V = uint32_t, class T>
+__device__ __forceinline__ __attribute__((address_space(1))) V* gword(T* base, uint32_t i)
+{
+    using Byte = __attribute__((address_space(1))) char;
+    return (__attribute__((address_space(1))) V*)((Byte*)base + i * 4u);
+}
+
 constexpr int kTileLog = 14;                 // largest LDS tile: 2^14 residues, 64 KB
 constexpr int kTileMinLog = 10;              // smallest tile of a multi-pass transform
 constexpr int kStridedMaxLog = 9;            // strided passes: <= 512 rows

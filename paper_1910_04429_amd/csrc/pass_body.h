@@ -147,13 +147,13 @@ __device__ __forceinline__ void source_quad(const BlockView& a, uint32_t pos, ui
         if (d0 + 4 * W <= D && (reinterpret_cast<uintptr_t>(a.digits) & 15u) == 0) {
 #pragma unroll
             for (int q = 0; q < W; ++q) {
-                const u32x4 t = *gmem(reinterpret_cast<const u32x4*>(a.digits + d0 + 4 * q));
+                const u32x4 t = *gword<const u32x4>(a.digits, d0 + 4 * q);
                 v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 4 * W; ++i)
-                if (d0 + i < D) v[i] = *gmem(a.digits + d0 + i);
+                if (d0 + i < D) v[i] = *gword(a.digits, d0 + i);
         }
     } else {
 #pragma unroll
@@ -333,7 +333,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
                 if (kHalf && n >= RHO / 2)
                     x[n] = 0u;
                 else
-                    x[n] = (kIO == 1) ? *gmem(io.in + base + n * nstep) : sm[sb ^ swz(n * nstep)];
+                    x[n] = (kIO == 1) ? *gword(io.in, base + n * nstep) : sm[sb ^ swz(n * nstep)];
             }
             dif_regs<R, PI, kHalf>(x);
             if (twiddle) {
@@ -367,7 +367,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
                 if (kHalf && n >= RHO / 2)
                     continue;
                 if (kIO == 2) {
-                    if (base + n * nstep < io.limit) *gmem(io.out + base + n * nstep) = x[n];
+                    if (base + n * nstep < io.limit) *gword(io.out, base + n * nstep) = x[n];
                 } else {
                     sm[sb ^ swz(n * nstep)] = x[n];
                 }
@@ -530,7 +530,7 @@ __device__ __forceinline__ void fused_middle(uint32_t* sm, int N, const uint32_t
         if (RHO >= 4) {
 #pragma unroll
             for (int v = 0; v < RHO / 4; ++v) {
-                const u32x4 w = *gmem(reinterpret_cast<const u32x4*>(chat + base + 4 * v));
+                const u32x4 w = *gword<const u32x4>(chat, base + 4 * v);
                 c[4 * v] = w.x;
                 c[4 * v + 1] = w.y;
                 c[4 * v + 2] = w.z;
@@ -538,7 +538,7 @@ __device__ __forceinline__ void fused_middle(uint32_t* sm, int N, const uint32_t
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < RHO; ++k) c[k] = *gmem(chat + base + k);
+            for (int k = 0; k < RHO; ++k) c[k] = *gword(chat, base + k);
         }
 #pragma unroll
         for (int k = 0; k < RHO; ++k) {
@@ -582,7 +582,7 @@ __device__ __forceinline__ void last_step_store(const uint32_t* sm, int N, uint3
 #pragma unroll
         for (int v = 0; v < RHO / 4; ++v)
             if (base + 4 * v < limit)
-                *gmem(reinterpret_cast<u32x4*>(out + base + 4 * v)) =
+                *gword<u32x4>(out, base + 4 * v) =
                     u32x4{y[4 * v], y[4 * v + 1], y[4 * v + 2], y[4 * v + 3]};
     }
 }
@@ -668,7 +668,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
         }
         uint4 v;
         if constexpr (!kSrc) {
-            const u32x4 t = *gmem(reinterpret_cast<const u32x4*>(data + pos));
+            const u32x4 t = *gword<const u32x4>(data, pos);
             v = make_uint4(t.x, t.y, t.z, t.w);
         } else if (bv.src == kSrcBits) {
             v.x = source_bit(bv, pos + 0);
@@ -758,7 +758,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
             v.w = fmul_shoup(v.w, w, q, p);
         }
         if (pos < bv.store_limit)
-            *gmem(reinterpret_cast<u32x4*>(data + pos)) = u32x4{v.x, v.y, v.z, v.w};
+            *gword<u32x4>(data, pos) = u32x4{v.x, v.y, v.z, v.w};
     }
 }
 

@@ -775,6 +775,7 @@ struct pa_batch {
         uint32_t chunks = 0;             // widest carry grid of the group
         int per = 4;
         uint64_t key_bytes = 0, coeffs = 0, out_bytes = 0, window = 0;
+        float tuned_ms = 0.f;            // pa_batch_tune: one run of the group alone
     };
     std::vector<Group> groups;
     JobDesc* d_jobs = nullptr;
@@ -1752,6 +1753,7 @@ int pa_batch_tune(pa_batch* b, int reps)
         int rc = timed(g.plan, &cur);
         if (rc) return rc;
         if (best_ms[bi] < cur) g.plan = plans[bi];
+        g.tuned_ms = std::min(best_ms[bi], cur) / (float)reps;
     }
     return PA_OK;
 }
@@ -1764,7 +1766,10 @@ int pa_batch_group(const pa_batch* b, size_t i, uint64_t* length, uint32_t* bloc
     const auto& g = b->groups[i];
     if (length) *length = g.plan.L;
     if (blocks) *blocks = g.count;
-    if (plan) describe(g.plan, plan);
+    if (plan) {
+        describe(g.plan, plan);
+        plan->ms = g.tuned_ms;
+    }
     return PA_OK;
 }
 

@@ -246,6 +246,9 @@ def test_tuned_batch_stays_exact(pa, ctx):
         after = batch.groups()
         assert [g["length"] for g in after] == [g["length"] for g in before]
         assert sum(g["blocks"] for g in after) == len(blocks)
+        assert all(g["ms"] == 0.0 for g in before)
+        # a group with more than one candidate geometry was timed
+        assert any(g["ms"] > 0.0 for g in after)
         batch.run()
         torch.cuda.synchronize()
         for b, j in zip(blocks, jobs):

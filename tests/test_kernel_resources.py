@@ -3,11 +3,14 @@
 No kernel of libpa may use scratch memory or spill VGPRs: private-memory
 traffic in a pass kernel is a silent several-fold slowdown.  Scalar registers
 that do not fit are kept in VGPR lanes (v_writelane / v_readlane, VALU
-instructions); the pass kernels may do that only outside the innermost loops
-that do the arithmetic (the per-DFT loops, at least 64 VALU instructions per
-iteration), where a reload would cost an instruction per butterfly group;
-the short load/store sweeps may reload a bound.  Caught here rather than on
-the GPU.
+instructions).  In the pass kernels that traffic must stay out of the
+innermost loops that do the arithmetic (the per-DFT loops, at least 64 VALU
+instructions per iteration) but for a stray reload or two that the register
+allocator places at a loop latch: at most 2 lane instructions per such loop
+and at most 1.5% of its VALU instructions.  (A kernel whose scalar registers
+are squeezed, as the one for all kinds of pass was, or one forced to eight
+waves per SIMD, has tens to hundreds of them per loop.)  The short load/store
+sweeps may reload a bound.  Caught here rather than on the GPU.
 """
 import os
 import re
@@ -81,9 +84,11 @@ def test_no_scratch_no_vgpr_spill(src, tmp_path):
         heavy = 0
         for a, b in loops:
             body = lines[a:b + 1]
-            if sum(1 for x in body if x.startswith("\tv_")) < 64:
+            valu = sum(1 for x in body if x.startswith("\tv_"))
+            if valu < 64:
                 continue
             heavy += 1
             lane = [x for x in body if "v_readlane_b32" in x or "v_writelane_b32" in x]
-            assert not lane, f"{k}: scalar-register spill traffic inside an arithmetic loop"
+            assert len(lane) <= 2 and len(lane) <= 0.015 * valu, \
+                f"{k}: scalar-register spill traffic inside an arithmetic loop: {lane}"
         assert heavy, k
