@@ -19,11 +19,13 @@
 //
 // Two launches, none of which waits on another workgroup: (1) every chunk of
 // digits loads its threads' residues, forms its column sums and scans its
-// threads' carry functions into the chunk's function; (2) every chunk composes
-// the functions of the chunks before it (a few thousand bytes) into its
-// carry-in, redoes (1), resolves its digits (and two past its end) and writes
-// every output word that starts inside the chunk.  Workgroups on different
-// XCDs never exchange data inside a kernel.
+// threads' carry functions into the chunk's function; a chunk that reaches the
+// output window also stores its column sums (34 bits each, in the multiplier
+// spectrum's array, free by then); (2) every such chunk composes the functions
+// of the chunks before it (a few thousand bytes) into its carry-in, reloads
+// its column sums, resolves its digits (and two past its end) and writes every
+// output word that starts inside the chunk.  Workgroups on different XCDs
+// never exchange data inside a kernel.
 #include "carry_body.h"
 
 namespace pa {

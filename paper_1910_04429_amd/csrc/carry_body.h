@@ -22,21 +22,30 @@ __device__ __forceinline__ uint32_t wave_scan(uint32_t f, int lane)
     return f;
 }
 
-__device__ __forceinline__ uint32_t addend_digit(const CarryArgs& a, uint32_t t)
+// Addend digits t and t + 1 (t even: the two halves of one 64-bit word of
+// d), low digit in the low half; 0 at and past D, the top digit masked to n bits.
+__device__ __forceinline__ uint64_t addend_pair(const CarryArgs& a, uint32_t t)
 {
-    if (t >= a.num_digits)
+    const uint32_t D = a.num_digits;
+    if (t >= D)
         return 0;
-    uint32_t v;
+    uint64_t w;
     if (a.addend_src == kSrcDigits) {
-        v = *gmem(a.addend + t);
+        const uint32_t lo = *gmem(a.addend + t);
+        const uint32_t hi = (t + 1 < D) ? *gmem(a.addend + t + 1) : 0u;
+        w = ((uint64_t)hi << 32) | lo;
     } else {
-        const uint64_t w = splitmix64(a.seed, t >> 1);
-        v = (t & 1) ? (uint32_t)(w >> 32) : (uint32_t)w;
+        w = splitmix64(a.seed, t >> 1);
     }
-    const uint32_t top = (uint32_t)(a.n & 31);
-    if (t == a.num_digits - 1 && top)
-        v &= (1u << top) - 1u;
-    return v;
+    // bits at and past n (the top digit's high bits, and digit t + 1 when t is
+    // the last digit)
+    const uint64_t keep = (uint64_t)D * 32 - a.n;   // bits of the top digit past n
+    const uint32_t last = D - 1;
+    if (t == last)
+        w &= (0xFFFFFFFFull >> keep);
+    else if (t + 1 == last)
+        w &= ~0ull >> keep;
+    return w;
 }
 
 // Exact coefficient from its residues over the first NP primes (Garner's mixed
@@ -98,6 +107,7 @@ __device__ __forceinline__ void bind_job(CarryArgs& a, uint32_t job)
         a.seed = j->seed_b;
     }
     a.desc = j->carry;
+    a.sums = j->A;
     a.out = j->out;
     a.chunks = j->chunks;
 }
@@ -134,42 +144,19 @@ struct CarryShared {
     uint32_t wpre[kCarryThreads / 64];
 };
 
-// One chunk of one block (job) of 256 threads.  kApply = false: write the
-// chunk's carry function.  kApply = true: resolve the chunk with its carry-in
-// and write its output words.  Returns early (uniformly) for chunks with
-// nothing to do.
-template <int kPer, bool kApply, int W>
-__device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_t job,
-                                            CarryShared<kPer, W>& sh)
+// Column sums s[i] of digits kf + i, i < count (0 at and past D), from the
+// residues: CRT of this thread's coefficients, the high words of the two
+// before its first from the previous thread through LDS.
+template <int kPer, int W>
+__device__ __forceinline__ void column_sums(const CarryArgs& a, int64_t k0, int64_t kf, int count,
+                                            uint64_t (&s)[kPer + 2], CarryShared<kPer, W>& sh)
 {
-    constexpr int NP = 2 * W + 1;              // primes, and words per coefficient
-    static_assert(kPer % W == 0, "a thread owns whole coefficients");
-    if (a.jobs) {
-        bind_job(a, job);
-        if (chunk >= a.chunks)
-            return;
-    }
-    constexpr int kChunk = kCarryThreads * kPer;
-    auto& val = sh.val;
-
-    const int tid = threadIdx.x;
-    const int64_t k0 = (int64_t)chunk * kChunk;
-    const uint32_t D = a.num_digits;
-    // A chunk below bit n - m writes no output word (none starts in it): its
-    // digits reach the output only through its carry function, which the local
-    // kernel has written.
-    if (kApply && (uint64_t)(k0 + kChunk) * 32 <= a.n - a.m)
-        return;
-
-    // column sums of this thread's kPer digits (and, for the last thread, the
-    // two digits past the chunk, which it resolves with the chunk's carry-out);
-    // its digits W K + r come from coefficients K, K - 1 and K - 2
+    constexpr int NP = 2 * W + 1;
     constexpr int kExtra = 2;
+    constexpr int kChunk = kCarryThreads * kPer;
     constexpr int kCo = kPer / W;              // coefficients per thread
-    uint64_t s[kPer + kExtra];
-    const int first = tid * kPer;
-    const int count = kPer + (tid == kCarryThreads - 1 ? kExtra : 0);
-    const int64_t kf = k0 + first;             // a multiple of W
+    const int tid = threadIdx.x;
+    const uint32_t D = a.num_digits;
     const int64_t K0 = kf / W;
     const int64_t coeffs = (D + W - 1) / W;
     // this thread's residues, vector loads when its coefficients lie inside
@@ -206,8 +193,9 @@ __device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_
     // Exact coefficients of this thread.  The high words of the two before its
     // first come from the previous thread through LDS; for thread 0 they are
     // the chunk's boundary coefficients, and the last thread's two extra digits
-    // need the coefficient past the chunk: lane 0 of waves 1, 2 and 3 computes
-    // one each, so that no wave runs more than one CRT beyond its own.
+    // need the coefficient past the chunk: lanes 0, 1 and 2 of wave 0 compute
+    // one each, in one pass of the wave (a single lane in each of three waves
+    // would cost three waves a pass each).
     uint32_t z[kCo][NP];
 #pragma unroll
     for (int ci = 0; ci < kCo; ++ci) {
@@ -221,22 +209,20 @@ __device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_
     // chunk
     auto& hw = sh.hw;
     auto& tail = sh.tail;
-    static_assert(kCarryThreads == 256, "boundary coefficients go to waves 1, 2 and 3");
 #pragma unroll
     for (int w = 0; w <= W; ++w) hw[tid + 1][w] = z[kCo - 1][W + w];
     hw[tid + 1][W + 1] = z[kCo - 2][2 * W];
-    {
+    if (tid < 3) {
         const int64_t Kc = k0 / W;             // first coefficient of the chunk
+        const int64_t K = tid == 0 ? Kc - 1 : (tid == 1 ? Kc - 2 : Kc + kChunk / W);
         uint32_t q[NP];
-        if (tid == 64) {
-            load_coeff<W>(a, Kc - 1, q);
+        load_coeff<W>(a, K, q);
+        if (tid == 0) {
 #pragma unroll
             for (int w = 0; w <= W; ++w) hw[0][w] = q[W + w];
-        } else if (tid == 128) {
-            load_coeff<W>(a, Kc - 2, q);
+        } else if (tid == 1) {
             hw[0][W + 1] = q[2 * W];
-        } else if (tid == 192) {
-            load_coeff<W>(a, Kc + kChunk / W, q);
+        } else {
             tail[0] = q[0];
             tail[1] = q[1];
         }
@@ -249,6 +235,7 @@ __device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_
 #pragma unroll
         for (int w = 0; w <= W; ++w) prev[w] = hw[tid][w];
         uint32_t prev2 = hw[tid][W + 1];
+        uint64_t dpair = 0;                    // addend digits i and i + 1, i even
 #pragma unroll
         for (int ci = 0; ci < kCo + 1; ++ci) {
             const bool own = ci < kCo;
@@ -258,7 +245,10 @@ __device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_
                 if (i < count && i < kPer + kExtra) {
                     const uint32_t zw = own ? z[ci % kCo][rr] : (rr < 2 ? tail[rr % 2] : 0u);
                     const int64_t k = kf + i;
-                    const uint32_t d = (k < (int64_t)D) ? addend_digit(a, (uint32_t)k) : 0u;
+                    // kf is even (kPer is), so digit pairs are word-aligned
+                    if ((i & 1) == 0)
+                        dpair = (k < (int64_t)D) ? addend_pair(a, (uint32_t)k) : 0ull;
+                    const uint32_t d = (i & 1) ? (uint32_t)(dpair >> 32) : (uint32_t)dpair;
                     s[i % (kPer + kExtra)] = (k < (int64_t)D)
                         ? (uint64_t)zw + prev[rr] + (rr == 0 ? prev2 : 0u) + d : 0ull;
                 }
@@ -269,6 +259,116 @@ __device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_
                 for (int w = 0; w <= W; ++w) prev[w] = z[ci % kCo][W + w];
             }
         }
+    }
+}
+
+// Store the column sums of this thread's kPer digits (those below D) for the
+// apply kernel: their low words at digit positions, their bits 32..33 packed
+// in one word per thread.  s < 2^34 (four terms below 2^32 each).
+template <int kPer>
+__device__ __forceinline__ void store_sums(const CarryArgs& a, int64_t kf, const uint64_t (&s)[kPer + 2])
+{
+    static_assert(kPer <= 16, "2 bits per digit in one word");
+    const uint32_t D = a.num_digits;
+    uint32_t hi = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) hi |= (uint32_t)(s[i] >> 32) << (2 * i);
+    if (kf + kPer <= (int64_t)D && kPer % 4 == 0) {
+#pragma unroll
+        for (int v = 0; v < kPer / 4; ++v)
+            *gword<u32x4>(a.sums, (uint32_t)kf + 4 * v) =
+                u32x4{(uint32_t)s[4 * v], (uint32_t)s[4 * v + 1], (uint32_t)s[4 * v + 2],
+                      (uint32_t)s[4 * v + 3]};
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i)
+            if (kf + i < (int64_t)D)
+                *gword(a.sums, (uint32_t)(kf + i)) = (uint32_t)s[i];
+    }
+    if (kf < (int64_t)D)
+        *gword(a.sums, sums_hi_offset(D) + (uint32_t)(kf / kPer)) = hi;
+}
+
+// The column sums stored by the local kernel: this thread's kPer digits, and
+// for the last thread of the chunk the two after them (the next chunk's first
+// two, stored by its first thread); 0 at and past D.
+template <int kPer>
+__device__ __forceinline__ void load_sums(const CarryArgs& a, int64_t kf, int count, uint64_t (&s)[kPer + 2])
+{
+    const uint32_t D = a.num_digits;
+#pragma unroll
+    for (int i = 0; i < kPer + 2; ++i) s[i] = 0;
+    if (kf >= (int64_t)D)
+        return;
+    const uint32_t hi = *gword(a.sums, sums_hi_offset(D) + (uint32_t)(kf / kPer));
+    if (kf + kPer <= (int64_t)D && kPer % 4 == 0) {
+#pragma unroll
+        for (int v = 0; v < kPer / 4; ++v) {
+            const u32x4 q = *gword<const u32x4>(a.sums, (uint32_t)kf + 4 * v);
+            s[4 * v] = q.x;
+            s[4 * v + 1] = q.y;
+            s[4 * v + 2] = q.z;
+            s[4 * v + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i)
+            if (kf + i < (int64_t)D) s[i] = *gword(a.sums, (uint32_t)(kf + i));
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) s[i] |= (uint64_t)((hi >> (2 * i)) & 3u) << 32;
+    if (count > kPer && kf + kPer < (int64_t)D) {
+        const uint32_t nhi = *gword(a.sums, sums_hi_offset(D) + (uint32_t)(kf / kPer) + 1u);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            if (kf + kPer + i < (int64_t)D)
+                s[kPer + i] = *gword(a.sums, (uint32_t)(kf + kPer + i)) |
+                              ((uint64_t)((nhi >> (2 * i)) & 3u) << 32);
+    }
+}
+
+// One chunk of one block (job) of 256 threads.  kApply = false: write the
+// chunk's carry function.  kApply = true: resolve the chunk with its carry-in
+// and write its output words.  Returns early (uniformly) for chunks with
+// nothing to do.
+template <int kPer, bool kApply, int W>
+__device__ __forceinline__ void carry_chunk(CarryArgs a, uint32_t chunk, uint32_t job,
+                                            CarryShared<kPer, W>& sh)
+{
+    static_assert(kPer % W == 0, "a thread owns whole coefficients");
+    if (a.jobs) {
+        bind_job(a, job);
+        if (chunk >= a.chunks)
+            return;
+    }
+    constexpr int kChunk = kCarryThreads * kPer;
+    auto& val = sh.val;
+
+    const int tid = threadIdx.x;
+    const int64_t k0 = (int64_t)chunk * kChunk;
+    const uint32_t D = a.num_digits;
+    // A chunk below bit n - m writes no output word (none starts in it): its
+    // digits reach the output only through its carry function, which the local
+    // kernel has written.
+    if (kApply && (uint64_t)(k0 + kChunk) * 32 <= a.n - a.m)
+        return;
+
+    // column sums of this thread's kPer digits (and, for the last thread, the
+    // two digits past the chunk, which it resolves with the chunk's carry-out);
+    // its digits W K + r come from coefficients K, K - 1 and K - 2
+    constexpr int kExtra = 2;
+    uint64_t s[kPer + kExtra];
+    const int first = tid * kPer;
+    const int count = kPer + (tid == kCarryThreads - 1 ? kExtra : 0);
+    const int64_t kf = k0 + first;             // a multiple of W
+    // The apply kernel resolves only the chunks that reach the output window
+    // (it returned above for the others); the local kernel stores their sums.
+    if constexpr (kApply) {
+        load_sums<kPer>(a, kf, count, s);
+    } else {
+        column_sums<kPer, W>(a, k0, kf, count, s, sh);
+        if ((uint64_t)(k0 + kChunk) * 32 > a.n - a.m)
+            store_sums<kPer>(a, kf, s);
     }
     uint32_t f = carry_fn_of_sum(s[0]);
 #pragma unroll

@@ -141,11 +141,23 @@ struct CarryArgs {
     const uint32_t* addend;    // kSrcDigits
     uint64_t seed;             // kSrcSeed
     uint32_t* desc;            // [chunks] carry function of each chunk
+    // column sums of the chunks the apply kernel resolves, written by the
+    // local kernel: word k = bits 0..31 of s_k (k < D), then from word
+    // sums_hi_offset(D) one word per thread holding bits 32..33 of each of its
+    // digits' sums (2 bits per digit, its first digit lowest).  The multiplier
+    // spectrum's array, free once the pointwise product is taken.
+    uint32_t* sums;
     uint64_t* out;             // ceil(m / 64) words
     uint32_t chunks;           // grid width (the largest chunk count in a batch)
     int per;                   // digits per thread (W = 2: 4 or 8; W = 3: 6 or 12)
     const JobDesc* jobs;       // batch mode: per-block fields from jobs[blockIdx.y]
 };
+
+// First word of the packed high bits in CarryArgs::sums for D digits.
+__host__ __device__ inline uint32_t sums_hi_offset(uint32_t num_digits)
+{
+    return (num_digits + 63u) & ~63u;
+}
 
 // Optional timing of one launch: events stamped by the dispatch itself
 // (hipExtLaunchKernelGGL), so no extra packets sit between the kernels.

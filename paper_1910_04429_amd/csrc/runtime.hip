@@ -128,9 +128,9 @@ uint64_t layout_key(uint64_t n)
     return (len.L() << 2) | (uint64_t)len.W;
 }
 
-// Coefficients the carry apply kernel reads for an n-bit block with an m-bit
-// output: those of the chunks that hold an output word's first bit (chunks
-// wholly below bit n - m return at once).
+// Coefficients of the chunks the carry apply kernel resolves for an n-bit
+// block with an m-bit output: those that hold an output word's first bit
+// (chunks wholly below bit n - m return at once).
 uint64_t window_coeffs(uint64_t n, uint64_t m, int W)
 {
     const uint64_t D = (n + 31) / 32;
@@ -430,6 +430,9 @@ struct Work {
     uint32_t* A = nullptr;
     uint32_t* B = nullptr;
     uint32_t* carry = nullptr;
+    uint32_t* sums = nullptr;          // the carry kernels' column sums (free after
+                                       // the pointwise product: A's array, or the
+                                       // context's when A is a cached multiplier)
     uint64_t* out = nullptr;
     // batch mode
     const JobDesc* jobs = nullptr;
@@ -627,6 +630,7 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
     ca.chunks = w.chunks;
     ca.per = w.per;
     ca.desc = w.carry;
+    ca.sums = w.sums;
     ca.out = w.out;
     ca.jobs = w.jobs;
     const uint64_t chunk_bytes = 4ull * w.chunks * batch;
@@ -644,8 +648,12 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
         pb->lds = std::max(pb->lds, persist_carry_lds_bytes(pl.W));
         return PA_OK;
     }
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + chunk_bytes, launch_carry_local(ca, stream, batch, ev_));
-    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, NP * 4ull * w.window + chunk_bytes + w.out_bytes,
+    // the window's column sums: a low word per digit, a word of high bits per
+    // thread; written by the local kernel, read by the apply kernel
+    const uint64_t sums_bytes = 4ull * w.window * pl.W + 4ull * ((w.window * pl.W + w.per - 1) / w.per);
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_LOCAL, outD + chunk_bytes + sums_bytes,
+              launch_carry_local(ca, stream, batch, ev_));
+    PA_LAUNCH(ctx, rec, PA_K_CARRY_APPLY, sums_bytes + chunk_bytes + w.out_bytes,
               launch_carry_apply(ca, stream, batch, ev_));
     return PA_OK;
 }
@@ -671,6 +679,7 @@ int enqueue(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* c_words, const u
     w.A = ctx->A;
     w.B = ctx->B;
     w.carry = ctx->status;
+    w.sums = ctx->A;
     w.out = d_out;
     w.chunks = chunks_of(digits_of(n), pl.W);
     w.per = carry_digits_per_thread((uint32_t)digits_of(n), pl.W);
@@ -713,6 +722,7 @@ int enqueue_block(pa_ctx* ctx, const BlockBufs& b, hipStream_t stream)
     w.A = b.A;
     w.B = b.B;
     w.carry = b.carry;
+    w.sums = b.A;
     w.out = b.out;
     w.chunks = chunks_of(digits_of(b.n), pl.W);
     w.per = carry_digits_per_thread((uint32_t)digits_of(b.n), pl.W);
@@ -1492,6 +1502,7 @@ int pa_hash_mul_async(pa_ctx* ctx, const pa_mul* mh, const uint64_t* d_key, uint
     w.A = mh->A;
     w.B = ctx->B;
     w.carry = ctx->status;
+    w.sums = ctx->A;                   // mh->A holds the cached spectrum
     w.out = d_out;
     w.chunks = chunks_of(digits_of(n), pl.W);
     w.per = carry_digits_per_thread((uint32_t)digits_of(n), pl.W);
