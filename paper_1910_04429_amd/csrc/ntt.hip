@@ -76,6 +76,7 @@ hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch, co
     if (a.primes < 1 || a.primes > (w3 ? 7 : 5)) return hipErrorInvalidValue;
     const unsigned primes = (unsigned)a.primes;
     const int kind = pass_kind(a);
+    if (!pass_kind_fits(a, kind)) return hipErrorInvalidValue;
     auto kernel = w3 ? pass_kernel<3>(kind) : pass_kernel<2>(kind);
     if (ev.start)
         hipExtLaunchKernelGGL(kernel, dim3(tiles, primes, batch), dim3(threads),

@@ -286,22 +286,30 @@ __device__ __forceinline__ uint32_t step_exponent(const StepGeo& g, uint32_t o, 
 }
 
 // One DIF (forward) or DIT (inverse) step of radix 2^R over every DFT of the tile.
-// Where a step's data comes from and goes to besides LDS: kIO = 1 reads the
-// inputs of a forward step from HBM (`in`, tile-relative), kIO = 2 writes the
-// outputs of an inverse step to HBM (`out`, positions below `limit`).
+// Where a step's data comes from and goes to besides LDS (kIO, bit flags):
+// kIoIn reads the step's inputs from HBM, kIoOut writes its outputs to HBM
+// (positions below `limit`), in the order the step would have read or written
+// the tile (natural for a forward step's inputs and an inverse step's outputs,
+// bit-reversed within each DFT for the others).  `in` and `out` point to the
+// tile's row 0, column 0 in the array, whose rows are 2^shift residues apart
+// (the pass's S; 0 for a contiguous pass, one column).
+constexpr int kIoIn = 1, kIoOut = 2;
 struct GlobalIO {
     const uint32_t* in;
     uint32_t* out;
     uint32_t limit;
+    int shift;
 };
 
 // kHalf (the first register step of an operand's first pass, or the last one
 // of the final inverse pass, power-of-two rows): elements n >= 2^R / 2 of every
 // DFT are rows >= R / 2 of the pass, positions >= L / 2 >= D: zero on input
 // (forward: not read) or never stored (inverse: not written).
-template <int R, bool kInv, int PI, int kIO = 0, bool kHalf = false>
+// kStrided: the tile has 4 or more columns and its rows are 2^io.shift apart
+// in the array; else it is one contiguous column (tile and array offsets agree).
+template <int R, bool kInv, int PI, int kIO = 0, bool kHalf = false, bool kStrided = false>
 __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, const Tables& tb,
-                                         const GlobalIO& io = GlobalIO{nullptr, nullptr, 0u})
+                                         const GlobalIO& io = GlobalIO{nullptr, nullptr, 0u, 0})
 {
     constexpr uint32_t p = PrimeConst<PI>::p, pneg = PrimeConst<PI>::pneg;
     constexpr int RHO = 1 << R;
@@ -323,6 +331,12 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
         const uint32_t base = (((beta << g.logB) + o) << g.logC) + c;
         const uint32_t nstep = 1u << (g.logSig + g.logC);
         const uint32_t sb = swz(base);
+        // the same elements in the array (kIO): rows 2^shift apart
+        uint32_t gbase = base, gstep = nstep;
+        if constexpr (kStrided) {
+            gbase = (((beta << g.logB) + o) << io.shift) + c;
+            gstep = 1u << (g.logSig + io.shift);
+        }
         uint32_t x[RHO];
         uint32_t b = b_fixed;  // Montgomery form of the twiddle base
         if (twiddle && !fixed_base)
@@ -333,7 +347,7 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
                 if (kHalf && n >= RHO / 2)
                     x[n] = 0u;
                 else
-                    x[n] = (kIO == 1) ? *gword(io.in, base + n * nstep) : sm[sb ^ swz(n * nstep)];
+                    x[n] = (kIO & kIoIn) ? *gword(io.in, gbase + n * gstep) : sm[sb ^ swz(n * nstep)];
             }
             dif_regs<R, PI, kHalf>(x);
             if (twiddle) {
@@ -346,12 +360,19 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
                 }
             }
 #pragma unroll
-            for (int j = 0; j < RHO; ++j)
-                sm[sb ^ swz(bitrev_c(j, R) * nstep)] = x[j];
+            for (int j = 0; j < RHO; ++j) {
+                if (kIO & kIoOut) {
+                    const uint32_t gi = gbase + bitrev_c(j, R) * gstep;
+                    if (gi < io.limit) *gword(io.out, gi) = x[j];
+                } else {
+                    sm[sb ^ swz(bitrev_c(j, R) * nstep)] = x[j];
+                }
+            }
         } else {
 #pragma unroll
             for (int j = 0; j < RHO; ++j)
-                x[j] = sm[sb ^ swz(bitrev_c(j, R) * nstep)];
+                x[j] = (kIO & kIoIn) ? *gword(io.in, gbase + bitrev_c(j, R) * gstep)
+                                     : sm[sb ^ swz(bitrev_c(j, R) * nstep)];
             if (twiddle) {
                 uint32_t w = b;
 #pragma unroll
@@ -366,8 +387,8 @@ __device__ __forceinline__ void run_step(uint32_t* sm, int N, const StepGeo& g, 
             for (int n = 0; n < RHO; ++n) {
                 if (kHalf && n >= RHO / 2)
                     continue;
-                if (kIO == 2) {
-                    if (base + n * nstep < io.limit) *gword(io.out, base + n * nstep) = x[n];
+                if (kIO & kIoOut) {
+                    if (gbase + n * gstep < io.limit) *gword(io.out, gbase + n * gstep) = x[n];
                 } else {
                     sm[sb ^ swz(n * nstep)] = x[n];
                 }
@@ -473,38 +494,52 @@ __device__ __forceinline__ StepGeo step_geo(const PassArgs& a, int si, uint32_t 
     return g;
 }
 
-// Step 0 of a contiguous pass with HBM input (forward) or output (inverse).
-template <bool kInv, int PI>
+// A step of radix 2^r with HBM input or output (kIO), kHalf as for run_step
+// (radix >= 4).
+template <bool kInv, int PI, int kIO, bool kHalf = false, bool kStrided = false>
 __device__ __forceinline__ void dispatch_step_io(int r, uint32_t* sm, int N, const StepGeo& g,
                                                  const Tables& tb, const GlobalIO& io)
 {
-    constexpr int kIO = kInv ? 2 : 1;
     switch (r) {
-    case 1: run_step<1, kInv, PI, kIO>(sm, N, g, tb, io); break;
-    case 2: run_step<2, kInv, PI, kIO>(sm, N, g, tb, io); break;
-    case 3: run_step<3, kInv, PI, kIO>(sm, N, g, tb, io); break;
-    case 4: run_step<4, kInv, PI, kIO>(sm, N, g, tb, io); break;
+    case 1: if constexpr (!kHalf) run_step<1, kInv, PI, kIO, false, kStrided>(sm, N, g, tb, io); break;
+    case 2: run_step<2, kInv, PI, kIO, kHalf, kStrided>(sm, N, g, tb, io); break;
+    case 3: run_step<3, kInv, PI, kIO, kHalf, kStrided>(sm, N, g, tb, io); break;
+    case 4: run_step<4, kInv, PI, kIO, kHalf, kStrided>(sm, N, g, tb, io); break;
     default: break;
     }
 }
 
-// Steps first .. count-1 of the pass (forward), or their inverse count-1 .. first.
-template <bool kInv, int PI>
+// Steps first .. count-1 of the pass (forward), or their inverse count-1 ..
+// first.  io_in: the first step run reads its inputs from HBM (no LDS load
+// before it); io_out: the last step run writes its outputs to HBM (and no
+// barrier follows it).  Both need power-of-two steps at those ends, and
+// count - first >= 2.
+template <bool kInv, int PI, bool kStrided = false>
 __device__ __forceinline__ void run_pass_steps(const PassArgs& a, uint32_t* sm, int N, uint32_t col0,
-                                               int count, int first = 0, bool half = false)
+                                               int count, int first = 0, bool half = false,
+                                               const GlobalIO& io = GlobalIO{nullptr, nullptr, 0u, 0},
+                                               bool io_in = false, bool io_out = false)
 {
     const int has3 = a.f == 3;
     for (int k = first; k < count; ++k) {
         const int si = kInv ? count - 1 - (k - first) : k;
         const StepGeo g = step_geo(a, si, col0);
         const int r = (int)((a.steps_code >> (4 * (si - has3))) & 15u);
+        const bool in = io_in && k == first, out = io_out && k == count - 1;
         if (has3 && si == 0)
             run_step3<kInv, PI>(sm, N, g, a.tb);
+        else if (in)
+            dispatch_step_io<kInv, PI, kIoIn, false, kStrided>(r, sm, N, g, a.tb, io);
+        else if (out && half && si == 0)
+            dispatch_step_io<kInv, PI, kIoOut, true, kStrided>(r, sm, N, g, a.tb, io);
+        else if (out)
+            dispatch_step_io<kInv, PI, kIoOut, false, kStrided>(r, sm, N, g, a.tb, io);
         else if (half && si == 0)
             dispatch_step_half<kInv, PI>(r, sm, N, g, a.tb);
         else
             dispatch_step<kInv, PI>(r, sm, N, g, a.tb);
-        __syncthreads();
+        if (!out)
+            __syncthreads();
     }
 }
 
@@ -603,8 +638,10 @@ __device__ __forceinline__ void dispatch_fused_middle(int r, uint32_t* sm, int N
 // have W 32-bit words per digit.  kMode is the pass's mode (a.mode) and kSrc
 // whether its input is an operand source rather than a residue array
 // (a.src != kSrcArray): fixed at compile time, so each kernel carries only
-// the code of its own kind of pass.
-template <int PI, int W, int kMode, bool kSrc>
+// the code of its own kind of pass.  kStrided: the pass is known to be strided
+// (a.s > 0, 4 or more columns per tile; the inverse passes after the fused
+// one), else the layout is read from the arguments.
+template <int PI, int W, int kMode, bool kSrc, bool kStrided>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const TileCoord& tc)
 {
     constexpr uint32_t p = PrimeConst<PI>::p;
@@ -632,12 +669,22 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
     // reads its first register step straight from HBM: lanes take consecutive
     // positions, so those loads coalesce, and the load sweep and its barrier go.
     const int total = a.nsteps + (a.f == 3);
-    const bool contig = a.f == 1 && logC == 0 && a.nsteps >= 2;
+    const bool many_cols = kStrided || logC >= 2;
+    const bool contig = !kStrided && a.f == 1 && logC == 0 && a.nsteps >= 2;
     const bool hbm_in = !kSrc && kMode != kInverse && contig;
     const StepGeo g0 = step_geo(a, 0, col0);
     const int r0 = (int)(a.steps_code & 15u);
-    const GlobalIO io{data + blk0, data + blk0,
-                      bv.store_limit > blk0 ? bv.store_limit - blk0 : 0u};
+    const uint32_t org = blk0 + col0;         // tile row 0, column 0 in the array
+    const GlobalIO io{data + org, data + org, bv.store_limit > org ? bv.store_limit - org : 0u,
+                      kStrided ? a.s : 0};
+    // An inverse strided pass likewise reads its first step's inputs from HBM
+    // and writes its last step's outputs (power-of-two rows) to HBM, instead
+    // of the load and store sweeps through LDS.  (Measured: the inverse pass
+    // at n = 10^8 44.7 -> 41.2 us; the same store in a forward strided pass,
+    // the operands' first passes, made them 2.5 us slower.)
+    const bool strided = kStrided && kMode == kInverse && total >= 2;
+    const bool s_in = strided;
+    const bool s_out = strided && a.f == 1;
 
     // An operand's first pass covers the whole array in one block of R rows;
     // rows >= R / 2 are positions >= L / 2 >= D, all zero: they are neither
@@ -655,9 +702,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
     // holds tile elements 4u .. 4u + 3.
     const int nq = N >> 2;
     const int nq_in = half_in ? nq >> 1 : nq;
-    for (int u = threadIdx.x; u < nq_in && !hbm_in; u += blockDim.x) {
+    for (int u = threadIdx.x; u < nq_in && !hbm_in && !s_in; u += blockDim.x) {
         uint32_t e, pos;
-        if (logC >= 2) {
+        if (many_cols) {
             const uint32_t row = (uint32_t)u >> (logC - 2);
             const uint32_t c = ((uint32_t)u << 2) & ((1u << logC) - 1u);
             e = (row << logC) + c;
@@ -693,12 +740,15 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
         *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
     }
     if (hbm_in) {
-        dispatch_step_io<false, PI>(r0, sm, N, g0, a.tb, io);
+        dispatch_step_io<false, PI, kIoIn>(r0, sm, N, g0, a.tb, io);
     }
-    __syncthreads();
+    if (!s_in)
+        __syncthreads();
 
     if constexpr (kMode == kInverse) {
-        run_pass_steps<true, PI>(a, sm, N, col0, total, 0, half_out);
+        run_pass_steps<true, PI, kStrided>(a, sm, N, col0, total, 0, half_out, io, s_in, s_out);
+        if (s_out)
+            return;
     } else if (kMode == kFused && hbm_in) {
         // as below, with the first forward step read from HBM and the last
         // inverse step (its inverse) written to HBM
@@ -707,7 +757,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
         dispatch_fused_middle<PI>(rl, sm, N, bv.other + (size_t)PI * a.L + blk0);
         __syncthreads();
         run_pass_steps<true, PI>(a, sm, N, col0, total - 1, 1);
-        dispatch_step_io<true, PI>(r0, sm, N, step_geo(a, 0, col0), a.tb, io);
+        dispatch_step_io<true, PI, kIoOut>(r0, sm, N, step_geo(a, 0, col0), a.tb, io);
         return;
     } else if (kMode == kFused) {
         // Forward steps but the last, then the last forward step, the
@@ -720,7 +770,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
         dispatch_fused_middle<PI>(rl, sm, N, bv.other + (size_t)PI * a.L + blk0);
         __syncthreads();
         run_pass_steps<true, PI>(a, sm, N, col0, total - 1);
-    } else if (a.f == 1 && logC == 0 && a.nsteps >= 2 && ((a.steps_code >> (4 * (a.nsteps - 1))) & 15u) >= 2) {
+    } else if (!kStrided && a.f == 1 && logC == 0 && a.nsteps >= 2 &&
+               ((a.steps_code >> (4 * (a.nsteps - 1))) & 15u) >= 2) {
         // forward contiguous pass: all steps but the last through LDS, the
         // last straight to HBM
         run_pass_steps<false, PI>(a, sm, N, col0, total - 1, hbm_in ? 1 : 0, half_in);
@@ -740,7 +791,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
 
     for (int u = threadIdx.x; u < (half_out ? nq >> 1 : nq); u += blockDim.x) {
         uint32_t e, pos;
-        if (logC >= 2) {
+        if (many_cols) {
             const uint32_t row = (uint32_t)u >> (logC - 2);
             const uint32_t c = ((uint32_t)u << 2) & ((1u << logC) - 1u);
             e = (row << logC) + c;
@@ -766,38 +817,40 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
 // five primes; also the Toeplitz variant's bit sources over prime 0) or W = 3
 // (96-bit digits, all seven).  The body is instantiated once per prime, so
 // that the prime's constants are immediates.
-template <int W, int kMode, bool kSrc>
+template <int W, int kMode, bool kSrc, bool kStrided>
 __device__ __forceinline__ void pass_tile_any(const PassArgs& a, uint32_t* sm, uint32_t prime,
                                               const TileCoord& tc)
 {
     if constexpr (W == 3) {
         switch (prime) {
-        case 0: pass_tile<0, W, kMode, kSrc>(a, sm, tc); break;
-        case 1: pass_tile<1, W, kMode, kSrc>(a, sm, tc); break;
-        case 2: pass_tile<2, W, kMode, kSrc>(a, sm, tc); break;
-        case 3: pass_tile<3, W, kMode, kSrc>(a, sm, tc); break;
-        case 4: pass_tile<4, W, kMode, kSrc>(a, sm, tc); break;
-        case 5: pass_tile<5, W, kMode, kSrc>(a, sm, tc); break;
-        default: pass_tile<6, W, kMode, kSrc>(a, sm, tc); break;
+        case 0: pass_tile<0, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 1: pass_tile<1, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 2: pass_tile<2, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 3: pass_tile<3, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 4: pass_tile<4, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 5: pass_tile<5, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        default: pass_tile<6, W, kMode, kSrc, kStrided>(a, sm, tc); break;
         }
     } else {
         switch (prime) {
-        case 0: pass_tile<0, W, kMode, kSrc>(a, sm, tc); break;
-        case 1: pass_tile<1, W, kMode, kSrc>(a, sm, tc); break;
-        case 2: pass_tile<2, W, kMode, kSrc>(a, sm, tc); break;
-        case 3: pass_tile<3, W, kMode, kSrc>(a, sm, tc); break;
-        default: pass_tile<4, W, kMode, kSrc>(a, sm, tc); break;
+        case 0: pass_tile<0, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 1: pass_tile<1, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 2: pass_tile<2, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 3: pass_tile<3, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        default: pass_tile<4, W, kMode, kSrc, kStrided>(a, sm, tc); break;
         }
     }
 }
 
-// The kinds of pass a plan has: (mode, operand source), see pass_tile.
+// The kinds of pass a plan has: (mode, operand source), see pass_tile.  Every
+// pass but the last of a transform is strided and the last is contiguous, so
+// the inverse passes after the fused one (the last) are all strided.
 enum PassKind : int {
     kKindFirst = 0,        // forward, from the operand (its first pass)
     kKindForward = 1,      // forward, residue array in place
     kKindFusedFirst = 2,   // fused, from the key (a one-pass transform)
     kKindFused = 3,        // fused, residue array in place
-    kKindInverse = 4,      // inverse
+    kKindInverse = 4,      // inverse, strided
     kPassKinds = 5,
 };
 
@@ -809,6 +862,13 @@ __host__ __device__ inline int pass_kind(const PassArgs& a)
     return src ? kKindFirst : kKindForward;
 }
 
+// Whether launch arguments fit their kind's kernel (the host checks before a
+// launch): the inverse kind needs a strided pass (a.s > 0, 4 or more columns).
+__host__ __device__ inline bool pass_kind_fits(const PassArgs& a, int kind)
+{
+    return kind != kKindInverse || (a.s > 0 && a.logC >= 2);
+}
+
 template <int W, int kKind>
 __device__ __forceinline__ void pass_tile_kind(const PassArgs& a, uint32_t* sm, uint32_t prime,
                                                const TileCoord& tc)
@@ -816,7 +876,7 @@ __device__ __forceinline__ void pass_tile_kind(const PassArgs& a, uint32_t* sm, 
     constexpr int kMode = kKind == kKindInverse ? kInverse
                         : (kKind == kKindFused || kKind == kKindFusedFirst) ? kFused : kForward;
     constexpr bool kSrc = kKind == kKindFirst || kKind == kKindFusedFirst;
-    pass_tile_any<W, kMode, kSrc>(a, sm, prime, tc);
+    pass_tile_any<W, kMode, kSrc, kKind == kKindInverse>(a, sm, prime, tc);
 }
 
 }  // namespace
