@@ -7,8 +7,12 @@
 // once and their kernels overlap on the device.  Budget memory is one
 // allocation made at creation and handed out first-fit, so admission never
 // calls hipMalloc.  The twiddle tables live on the device for the server's
-// lifetime (its own context).  A scheduler thread drives everything; callers
-// only touch a mutex-protected queue.
+// lifetime (its own context).  A scheduler thread admits requests, queues
+// their device work and retires them; callers only touch a mutex-protected
+// queue.  For host requests each slot has a copy thread that moves the key
+// into the slot's pinned staging buffer and the result out of it, so that
+// those copies (megabytes each) run beside each other and never hold up the
+// scheduler.
 #include <stdio.h>
 #include <string.h>
 
@@ -17,6 +21,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -45,6 +50,11 @@ struct Request {
     bool done = false;
 };
 
+// Where a slot's request is (transitions under the server's mutex):
+// free -> [host: staging in (copy thread) -> staged] -> running (device work
+// queued) -> [host: staging out (copy thread) -> copied] -> free.
+enum Phase : int { kFree, kStageIn, kStaged, kRunning, kStageOut, kCopied };
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -52,6 +62,9 @@ struct Slot {
     uint64_t* out_stage = nullptr;
     Request* req = nullptr;
     uint64_t off = 0, bytes = 0;
+    Phase phase = kFree;
+    std::condition_variable cv;      // wakes the copy thread
+    std::thread copier;
 };
 
 double ms_between(Clock::time_point a, Clock::time_point b)
@@ -66,7 +79,7 @@ struct pa_server {
     pa_server_opts opts{};
     uint8_t* pool = nullptr;
     pa::Arena* arena = nullptr;
-    std::vector<Slot> slots;
+    std::vector<std::unique_ptr<Slot>> slots;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request*> pending;
@@ -75,6 +88,7 @@ struct pa_server {
     std::vector<double> lat_ok;         // latency of every completed request
     uint64_t next_ticket = 1;
     bool stop = false;
+    bool stop_copiers = false;
     std::thread worker;
     // stats (guarded by mu)
     uint64_t completed = 0, failed = 0, bits = 0, admitted_peak = 0;
@@ -92,14 +106,13 @@ uint64_t footprint(const pa_server* s, const Request& r)
     return b;
 }
 
-// Start request r on slot sl (scheduler thread).  Returns a PA_* code.
-int start(pa_server* s, Slot& sl, Request* r, uint64_t off, uint64_t bytes)
+// Queue the device work of slot sl's request (scheduler thread): for a host
+// request its key is in the slot's staging buffer.  Returns a PA_* code.
+int start_gpu(pa_server* s, Slot& sl)
 {
     pa_ctx* ctx = s->ctx;
-    sl.req = r;
-    sl.off = off;
-    sl.bytes = bytes;
-    uint8_t* base = s->pool + off;
+    Request* r = sl.req;
+    uint8_t* base = s->pool + sl.off;
     BlockBufs b;
     block_layout(r->n, base, &b);
     const uint64_t* dkey = r->key;
@@ -108,7 +121,6 @@ int start(pa_server* s, Slot& sl, Request* r, uint64_t off, uint64_t bytes)
         uint8_t* io = base + block_workspace_bytes(r->n);
         uint64_t* kbuf = reinterpret_cast<uint64_t*>(io);
         dout = reinterpret_cast<uint64_t*>(io + round256(nwords(r->n) * 8));
-        memcpy(sl.in_stage, r->key, nwords(r->n) * 8);
         if (hipMemcpyAsync(kbuf, sl.in_stage, nwords(r->n) * 8, hipMemcpyHostToDevice,
                            sl.stream) != hipSuccess)
             return PA_EDEVICE;
@@ -133,12 +145,51 @@ int start(pa_server* s, Slot& sl, Request* r, uint64_t off, uint64_t bytes)
     return PA_OK;
 }
 
+// A slot's copy thread: the host copies of its requests.
+void copier(pa_server* s, Slot* sl)
+{
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        sl->cv.wait(lk, [&] {
+            return s->stop_copiers || sl->phase == kStageIn || sl->phase == kStageOut;
+        });
+        if (s->stop_copiers) return;
+        const Request* r = sl->req;
+        const bool in = sl->phase == kStageIn;
+        lk.unlock();
+        if (in)
+            memcpy(sl->in_stage, r->key, nwords(r->n) * 8);
+        else
+            memcpy(r->out, sl->out_stage, nwords(r->m) * 8);
+        lk.lock();
+        sl->phase = in ? kStaged : kCopied;
+        s->cv_work.notify_one();
+    }
+}
+
+Phase phase_of(pa_server* s, const Slot& sl)
+{
+    std::lock_guard<std::mutex> lk(s->mu);
+    return sl.phase;
+}
+
+void set_phase(pa_server* s, Slot& sl, Phase ph)
+{
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        sl.phase = ph;
+    }
+    if (ph == kStageIn || ph == kStageOut) sl.cv.notify_one();
+}
+
+// Retire slot sl's request (scheduler thread); for a host request its result
+// is already in the caller's buffer.
 void finish(pa_server* s, Slot& sl, int status)
 {
     Request* r = sl.req;
-    if (status == PA_OK && !r->device) memcpy(r->out, sl.out_stage, nwords(r->m) * 8);
     s->arena->release(sl.off, sl.bytes);
     std::lock_guard<std::mutex> lk(s->mu);
+    sl.phase = kFree;
     r->finished = Clock::now();
     r->status = status;
     r->done = true;
@@ -158,17 +209,39 @@ void finish(pa_server* s, Slot& sl, int status)
 void scheduler(pa_server* s)
 {
     (void)hipSetDevice(s->ctx->device);
+    // queue the device work of a slot whose request is ready for it
+    auto launch = [&](Slot& sl) {
+        const int rc = start_gpu(s, sl);
+        if (rc != PA_OK) {
+            (void)hipStreamSynchronize(sl.stream);
+            finish(s, sl, rc);
+            return;
+        }
+        set_phase(s, sl, kRunning);
+    };
     for (;;) {
         bool progress = false;
-        // retire finished slots
-        for (auto& sl : s->slots) {
-            if (!sl.req) continue;
-            const hipError_t q = hipEventQuery(sl.done);
-            if (q == hipSuccess) {
-                finish(s, sl, PA_OK);
+        for (auto& p : s->slots) {
+            Slot& sl = *p;
+            const Phase ph = phase_of(s, sl);
+            if (ph == kStaged) {
+                launch(sl);
                 progress = true;
-            } else if (q != hipErrorNotReady) {
-                finish(s, sl, PA_EDEVICE);
+            } else if (ph == kRunning) {
+                // retire finished device work
+                const hipError_t q = hipEventQuery(sl.done);
+                if (q == hipSuccess) {
+                    if (sl.req->device)
+                        finish(s, sl, PA_OK);
+                    else
+                        set_phase(s, sl, kStageOut);
+                    progress = true;
+                } else if (q != hipErrorNotReady) {
+                    finish(s, sl, PA_EDEVICE);
+                    progress = true;
+                }
+            } else if (ph == kCopied) {
+                finish(s, sl, PA_OK);
                 progress = true;
             }
         }
@@ -181,9 +254,9 @@ void scheduler(pa_server* s)
                 r = s->pending.front();
             }
             Slot* free_slot = nullptr;
-            for (auto& sl : s->slots)
-                if (!sl.req) {
-                    free_slot = &sl;
+            for (auto& p : s->slots)
+                if (!p->req) {
+                    free_slot = p.get();
                     break;
                 }
             if (!free_slot) break;
@@ -194,23 +267,25 @@ void scheduler(pa_server* s)
                 std::lock_guard<std::mutex> lk(s->mu);
                 s->pending.pop_front();
             }
-            const int rc = start(s, *free_slot, r, off, bytes);
-            if (rc != PA_OK) {
-                (void)hipStreamSynchronize(free_slot->stream);
-                finish(s, *free_slot, rc);
-            }
+            free_slot->req = r;
+            free_slot->off = off;
+            free_slot->bytes = bytes;
+            if (r->device)
+                launch(*free_slot);
+            else
+                set_phase(s, *free_slot, kStageIn);
             progress = true;
             uint64_t inflight = 0;
-            for (auto& sl : s->slots) inflight += sl.req != nullptr;
+            for (auto& p : s->slots) inflight += p->req != nullptr;
             std::lock_guard<std::mutex> lk(s->mu);
             s->admitted_peak = std::max(s->admitted_peak, inflight);
         }
         bool busy = false;
-        for (auto& sl : s->slots) busy |= sl.req != nullptr;
+        for (auto& p : s->slots) busy |= p->req != nullptr;
         std::unique_lock<std::mutex> lk(s->mu);
         if (s->stop && !busy && s->pending.empty()) return;
         if (!progress) {
-            if (busy)   // kernels in flight: poll again shortly
+            if (busy)   // kernels or copies in flight: poll again shortly
                 s->cv_work.wait_for(lk, std::chrono::microseconds(20));
             else
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(5),
@@ -234,9 +309,18 @@ void pa_server_destroy(pa_server* s)
         s->cv_work.notify_all();
         s->worker.join();
     }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop_copiers = true;
+    }
+    for (auto& p : s->slots) {
+        p->cv.notify_all();
+        if (p->copier.joinable()) p->copier.join();
+    }
     if (s->ctx) {
         (void)hipSetDevice(s->ctx->device);
-        for (auto& sl : s->slots) {
+        for (auto& p : s->slots) {
+            Slot& sl = *p;
             if (sl.stream) (void)hipStreamSynchronize(sl.stream);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
@@ -279,8 +363,14 @@ int pa_server_create(int device, const pa_server_opts* opts, pa_server** out)
         pa_server_destroy(s);
         return PA_ENOMEM;
     }
-    s->slots.resize(opts->slots);
-    for (auto& sl : s->slots) {
+    for (int i = 0; i < opts->slots; ++i) {
+        s->slots.emplace_back(new (std::nothrow) Slot);
+        if (!s->slots.back()) {
+            s->slots.pop_back();
+            pa_server_destroy(s);
+            return PA_ENOMEM;
+        }
+        Slot& sl = *s->slots.back();
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc(&sl.in_stage, nwords(opts->max_n) * 8, hipHostMallocDefault) != hipSuccess ||
@@ -288,6 +378,7 @@ int pa_server_create(int device, const pa_server_opts* opts, pa_server** out)
             pa_server_destroy(s);
             return PA_EDEVICE;
         }
+        sl.copier = std::thread(copier, s, &sl);
     }
     s->worker = std::thread(scheduler, s);
     *out = s;
