@@ -142,6 +142,21 @@ def test_plan_lengths_cover_the_linear_convolution():
     assert pa.pa_transform_length(350_000_000) == 3 << 22
 
 
+def test_carry_sums_fit_in_the_multiplier_spectrum():
+    """The carry kernels keep the output window's column sums in the
+    multiplier spectrum's array (free after the pointwise product): a low word
+    per 32-bit digit (D of them, padded to 64), then a word of high bits per
+    carry thread (4 or more digits each).  That array holds (2 W + 1) L >= 5 L
+    words for every block size, the smallest transforms included."""
+    import paper_1910_04429_amd as pa
+    for n in list(range(1, 4200, 37)) + [65_536, 1_000_003, 10**8, 301_989_888, 350_000_000,
+                                          pa.PA_MAX_N] + \
+            [int(x) for x in np.geomspace(1e4, pa.PA_MAX_N, 60)]:
+        D = (n + 31) // 32
+        need = ((D + 63) // 64) * 64 + (D + 3) // 4
+        assert need <= 5 * pa.pa_transform_length(n), n
+
+
 def _write_counter_csv(d, counter, rows):
     os.makedirs(d, exist_ok=True)
     with open(os.path.join(d, "run_counter_collection.csv"), "w") as f:
