@@ -14,11 +14,15 @@
 // adjacent columns per tile so that every row segment is a full 128-byte line.
 //
 // Inside a tile the length-R transform is itself split into steps of radix
-// 2^r <= 16 (68 registers per lane: seven waves per SIMD).  A step loads each of its small DFTs from LDS into registers, runs
-// the radix-2 butterflies there with the omega_64 powers (compile-time
-// constants of the prime, so scalar immediates), multiplies output k by b^k
-// for a per-DFT base b, and writes back.  The kernel body is instantiated once
-// per prime and the workgroup picks its prime from blockIdx.y.
+// 2^r <= 16 (64 to 68 vector registers per lane: seven waves per SIMD).  A
+// step loads each of its small DFTs from LDS into registers, runs the radix-2
+// butterflies there with the omega_64 powers (compile-time constants of the
+// prime), multiplies output k by b^k for a per-DFT base b, and writes back.
+// The first step of a pass whose input is a residue array may read its DFTs
+// straight from HBM, and the last step of a contiguous or inverse strided
+// pass may write straight to HBM (see pass_tile).  The kernel body is
+// instantiated once per prime and the workgroup picks its prime from
+// blockIdx.y.
 // For DIF step s on sub-blocks of size B split as n = n_s sigma + o the base is
 // omega_B^o; a strided pass also folds its omega_{RS}^{j k} factor into the
 // bases of its steps, so there is no separate twiddle sweep.
