@@ -111,7 +111,9 @@ struct PassArgs {
     // kernel argument is ever indexed at run time
     uint32_t steps_code, above_code;
     int mode, src;
-    int scale;                 // multiply the stored output by scale_w (Shoup)
+    int scale_in;              // multiply the source values by scale_w (Shoup; an
+                               // operand's first pass, not the dual launch's second
+                               // operand)
     uint32_t scale_w[kNumPrimes], scale_q[kNumPrimes];
     Tables tb;
     int primes;                // primes transformed (grid.y): 2 W + 1, or 1 (Toeplitz)

@@ -590,13 +590,12 @@ __device__ __forceinline__ void fused_middle(uint32_t* sm, int N, const uint32_t
 // The last step of a forward contiguous pass (radix 2^R >= 4 over 2^R
 // consecutive residues, no twiddles) straight to HBM: output k of the DFT at
 // base goes to position base + bitrev(k), so each thread writes 2^R
-// consecutive residues with 16-byte stores (scaled when asked) and the tile
-// skips its last LDS round trip and the store sweep.
+// consecutive residues with 16-byte stores and the tile skips its last LDS
+// round trip and the store sweep.
 template <int R, int PI>
 __device__ __forceinline__ void last_step_store(const uint32_t* sm, int N, uint32_t* out,
-                                                uint32_t limit, bool scale, uint32_t sw, uint32_t sq)
+                                                uint32_t limit)
 {
-    constexpr uint32_t p = PrimeConst<PI>::p;
     constexpr int RHO = 1 << R;
     static_assert(RHO >= 4, "16-byte stores");
     const int ndft = N >> R;
@@ -610,10 +609,7 @@ __device__ __forceinline__ void last_step_store(const uint32_t* sm, int N, uint3
         dif_regs<R, PI>(x);
         uint32_t y[RHO];
 #pragma unroll
-        for (int k = 0; k < RHO; ++k) {
-            const uint32_t v = x[bitrev_c(k, R)];
-            y[k] = scale ? fmul_shoup(v, sw, sq, p) : v;
-        }
+        for (int k = 0; k < RHO; ++k) y[k] = x[bitrev_c(k, R)];
 #pragma unroll
         for (int v = 0; v < RHO / 4; ++v)
             if (base + 4 * v < limit)
@@ -702,6 +698,10 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
     // holds tile elements 4u .. 4u + 3.
     const int nq = N >> 2;
     const int nq_in = half_in ? nq >> 1 : nq;
+    // the multiplier's factor on its source values (not the key's, which the
+    // dual launch runs as operand z = 1 with the same arguments)
+    const bool scale_in = kSrc && a.scale_in && !(a.dual && tc.z == 1);
+    const uint32_t sw_in = a.scale_w[PI], sq_in = a.scale_q[PI];
     for (int u = threadIdx.x; u < nq_in && !hbm_in && !s_in; u += blockDim.x) {
         uint32_t e, pos;
         if (many_cols) {
@@ -736,6 +736,14 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
             v.y = reduce64<PI>(h[2], h[3]);
             v.z = reduce64<PI>(h[4], h[5]);
             v.w = reduce64<PI>(h[6], h[7]);
+        }
+        if constexpr (kSrc) {
+            if (scale_in) {
+                v.x = fmul_shoup(v.x, sw_in, sq_in, p);
+                v.y = fmul_shoup(v.y, sw_in, sq_in, p);
+                v.z = fmul_shoup(v.z, sw_in, sq_in, p);
+                v.w = fmul_shoup(v.w, sw_in, sq_in, p);
+            }
         }
         *reinterpret_cast<uint4*>(&sm[swz(e)]) = v;
     }
@@ -777,13 +785,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
         run_pass_steps<false, PI>(a, sm, N, col0, total - 1, hbm_in ? 1 : 0, half_in);
         const int rl = (int)((a.steps_code >> (4 * (a.nsteps - 1))) & 15u);
         const uint32_t lim = bv.store_limit > blk0 ? bv.store_limit - blk0 : 0u;
-        const uint32_t sw = a.scale_w[PI], sq = a.scale_q[PI];
         if (rl == 2)
-            last_step_store<2, PI>(sm, N, data + blk0, lim, a.scale != 0, sw, sq);
+            last_step_store<2, PI>(sm, N, data + blk0, lim);
         else if (rl == 3)
-            last_step_store<3, PI>(sm, N, data + blk0, lim, a.scale != 0, sw, sq);
+            last_step_store<3, PI>(sm, N, data + blk0, lim);
         else
-            last_step_store<4, PI>(sm, N, data + blk0, lim, a.scale != 0, sw, sq);
+            last_step_store<4, PI>(sm, N, data + blk0, lim);
         return;
     } else {
         run_pass_steps<false, PI>(a, sm, N, col0, total, hbm_in ? 1 : 0, half_in);
@@ -800,14 +807,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
             e = (uint32_t)u << 2;
             pos = blk0 + e;
         }
-        uint4 v = *reinterpret_cast<const uint4*>(&sm[swz(e)]);
-        if (a.scale) {
-            const uint32_t w = a.scale_w[PI], q = a.scale_q[PI];
-            v.x = fmul_shoup(v.x, w, q, p);
-            v.y = fmul_shoup(v.y, w, q, p);
-            v.z = fmul_shoup(v.z, w, q, p);
-            v.w = fmul_shoup(v.w, w, q, p);
-        }
+        const uint4 v = *reinterpret_cast<const uint4*>(&sm[swz(e)]);
         if (pos < bv.store_limit)
             *gword<u32x4>(data, pos) = u32x4{v.x, v.y, v.z, v.w};
     }

@@ -393,7 +393,7 @@ bool make_plan(Len len, Plan* pl, unsigned blocks = 1, PlanParams pp = {})
         pl->nsteps[i] = plan_steps(pl->r[i], pl->steps[i], strided);
         if (pl->nsteps[i] > kMaxSteps) return false;
     }
-    // c-hat is scaled on its last pass by 2^32 / L so that the Montgomery
+    // c-hat is scaled by 2^32 / L (on the digits its first pass reads) so that the Montgomery
     // pointwise product yields x-hat c-hat / L.
     for (int pi = 0; pi < kNumPrimes; ++pi) {
         const uint64_t p = kPrimes[pi];
@@ -545,8 +545,11 @@ int enqueue_plan(pa_ctx* ctx, const Plan& pl, const Work& w, hipStream_t stream,
                 a.seed = w.seed_a;
             }
         }
-        if (i == P - 1) {
-            a.scale = 1;
+        if (i == 0) {
+            // c-hat's factor 2^32 / L (for the Montgomery pointwise product),
+            // applied to c's digits as its first pass reads them: the
+            // transform is linear, and half of the first pass's rows are zero
+            a.scale_in = 1;
             for (int pi = 0; pi < kNumPrimes; ++pi) {
                 a.scale_w[pi] = pl.scale_w[pi];
                 a.scale_q[pi] = pl.scale_q[pi];
@@ -989,9 +992,8 @@ int enqueue_toeplitz(pa_ctx* ctx, const uint64_t* d_key, const uint64_t* d_t, ui
                 a.digits = reinterpret_cast<const uint32_t*>(d_t);
                 a.bit_off = n - j0 - w;
                 a.n = need;
-            }
-            if (i == P - 1) {
-                a.scale = 1;
+                // t-hat's factor 2^32 / L, on its bits as they are read
+                a.scale_in = 1;
                 a.scale_w[0] = pl.scale_w[0];
                 a.scale_q[0] = pl.scale_q[0];
             }
