@@ -45,24 +45,29 @@ namespace {
 // One kernel per layout: W = 2 (64-bit digits, the first five primes; also the
 // Toeplitz variant's bit sources over prime 0) and W = 3 (96-bit digits, all
 // seven), so that neither carries the other's primes and sources.
-// Each kind of pass (pass_kind) has its own instance, so a kernel holds only
-// the code of one kind.
-template <int W, int kKind>
+// Each kind of pass (pass_kind) has its own instance, one for single blocks
+// and one for batches (block from the job table; kJobs of block_view), so a
+// kernel holds only the code of one kind.  The one-pass fused kind, which
+// serves short blocks only, has one instance for both (kJobs 2): compiled for
+// single blocks alone, its register allocation put scalar-spill reloads in
+// its arithmetic loop.
+template <int W, int kKind, int kJobs>
 __global__ __launch_bounds__(kPassThreads) void k_pass(const PassArgs a)
 {
     extern __shared__ uint32_t sm[];          // 4 N bytes
-    pass_tile_kind<W, kKind>(a, sm, blockIdx.y, TileCoord{blockIdx.x, gridDim.x, blockIdx.z, true});
+    pass_tile_kind<W, kKind, kJobs>(a, sm, blockIdx.y,
+                                    TileCoord{blockIdx.x, gridDim.x, blockIdx.z, true});
 }
 
-template <int W>
+template <int W, int kJobs>
 void (*pass_kernel(int kind))(PassArgs)
 {
     switch (kind) {
-    case kKindFirst: return k_pass<W, kKindFirst>;
-    case kKindForward: return k_pass<W, kKindForward>;
-    case kKindFusedFirst: return k_pass<W, kKindFusedFirst>;
-    case kKindFused: return k_pass<W, kKindFused>;
-    default: return k_pass<W, kKindInverse>;
+    case kKindFirst: return k_pass<W, kKindFirst, kJobs>;
+    case kKindForward: return k_pass<W, kKindForward, kJobs>;
+    case kKindFusedFirst: return k_pass<W, kKindFusedFirst, 2>;
+    case kKindFused: return k_pass<W, kKindFused, kJobs>;
+    default: return k_pass<W, kKindInverse, kJobs>;
     }
 }
 
@@ -81,7 +86,9 @@ hipError_t launch_pass(const PassArgs& a, hipStream_t stream, unsigned batch, co
     const unsigned primes = (unsigned)a.primes;
     const int kind = pass_kind(a);
     if (!pass_kind_fits(a, kind)) return hipErrorInvalidValue;
-    auto kernel = w3 ? pass_kernel<3>(kind) : pass_kernel<2>(kind);
+    const bool jobs = a.jobs != nullptr;
+    auto kernel = w3 ? (jobs ? pass_kernel<3, 1>(kind) : pass_kernel<3, 0>(kind))
+                     : (jobs ? pass_kernel<2, 1>(kind) : pass_kernel<2, 0>(kind));
     if (ev.start)
         hipExtLaunchKernelGGL(kernel, dim3(tiles, primes, batch), dim3(threads),
                               sizeof(uint32_t) * N, stream, ev.start, ev.stop, 0, a);

@@ -100,29 +100,40 @@ struct TileCoord {
     bool xcd_order;   // tiles were dealt to the XCDs round-robin by index
 };
 
+// The block a workgroup works on.  kJobs 0: a single block (the scalar
+// fields, or the dual launch's second operand); 1: a batch's block from the
+// job table (a.jobs set); 2: either, decided from a.jobs at run time.  The
+// kernels of most kinds are compiled apart for single blocks and batches, so
+// that the single-block ones carry no job-table code.
+__device__ __forceinline__ void job_view(const PassArgs& a, uint32_t z, BlockView& v)
+{
+    const auto* j = gmem(a.jobs + z);
+    v.n = j->n;
+    v.num_digits = j->num_digits;
+    v.data = (a.role == kRoleMul) ? j->A : j->B;
+    v.other = j->A;
+    if (a.src != kSrcArray) {             // first pass: the operand's digits
+        if (a.role == kRoleKey) {
+            v.src = kSrcDigits;
+            v.digits = j->key;
+        } else if (j->c) {
+            v.src = kSrcDigits;
+            v.digits = j->c;
+        } else {
+            v.src = kSrcSeed;
+            v.seed = j->seed_a;
+        }
+    }
+    if (a.limit_to_digits)
+        v.store_limit = ((j->num_digits + a.dwords - 1u) / a.dwords + 3u) & ~3u;
+}
+
+template <int kJobs>
 __device__ __forceinline__ BlockView block_view(const PassArgs& a, uint32_t z)
 {
     BlockView v{a.data, a.other, a.digits, a.seed, a.n, a.bit_off, a.num_digits, a.store_limit, a.src};
-    if (a.jobs) {
-        const auto* j = gmem(a.jobs + z);
-        v.n = j->n;
-        v.num_digits = j->num_digits;
-        v.data = (a.role == kRoleMul) ? j->A : j->B;
-        v.other = j->A;
-        if (a.src != kSrcArray) {             // first pass: the operand's digits
-            if (a.role == kRoleKey) {
-                v.src = kSrcDigits;
-                v.digits = j->key;
-            } else if (j->c) {
-                v.src = kSrcDigits;
-                v.digits = j->c;
-            } else {
-                v.src = kSrcSeed;
-                v.seed = j->seed_a;
-            }
-        }
-        if (a.limit_to_digits)
-            v.store_limit = ((j->num_digits + a.dwords - 1u) / a.dwords + 3u) & ~3u;
+    if (kJobs == 1 || (kJobs == 2 && a.jobs)) {
+        job_view(a, z, v);
     } else if (a.dual && z == 1) {
         v.data = const_cast<uint32_t*>(a.other);
         v.src = kSrcDigits;
@@ -637,11 +648,11 @@ __device__ __forceinline__ void dispatch_fused_middle(int r, uint32_t* sm, int N
 // the code of its own kind of pass.  kStrided: the pass is known to be strided
 // (a.s > 0, 4 or more columns per tile; the inverse passes after the fused
 // one), else the layout is read from the arguments.
-template <int PI, int W, int kMode, bool kSrc, bool kStrided>
+template <int PI, int W, int kMode, bool kSrc, bool kStrided, int kJobs>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const TileCoord& tc)
 {
     constexpr uint32_t p = PrimeConst<PI>::p;
-    const BlockView bv = block_view(a, tc.z);
+    const BlockView bv = block_view<kJobs>(a, tc.z);
     uint32_t* data = bv.data + (size_t)PI * a.L;
 
     const int logC = a.logC;                  // columns per tile
@@ -817,27 +828,27 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint32_t* sm, const
 // five primes; also the Toeplitz variant's bit sources over prime 0) or W = 3
 // (96-bit digits, all seven).  The body is instantiated once per prime, so
 // that the prime's constants are immediates.
-template <int W, int kMode, bool kSrc, bool kStrided>
+template <int W, int kMode, bool kSrc, bool kStrided, int kJobs>
 __device__ __forceinline__ void pass_tile_any(const PassArgs& a, uint32_t* sm, uint32_t prime,
                                               const TileCoord& tc)
 {
     if constexpr (W == 3) {
         switch (prime) {
-        case 0: pass_tile<0, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        case 1: pass_tile<1, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        case 2: pass_tile<2, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        case 3: pass_tile<3, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        case 4: pass_tile<4, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        case 5: pass_tile<5, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        default: pass_tile<6, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 0: pass_tile<0, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        case 1: pass_tile<1, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        case 2: pass_tile<2, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        case 3: pass_tile<3, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        case 4: pass_tile<4, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        case 5: pass_tile<5, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        default: pass_tile<6, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
         }
     } else {
         switch (prime) {
-        case 0: pass_tile<0, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        case 1: pass_tile<1, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        case 2: pass_tile<2, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        case 3: pass_tile<3, W, kMode, kSrc, kStrided>(a, sm, tc); break;
-        default: pass_tile<4, W, kMode, kSrc, kStrided>(a, sm, tc); break;
+        case 0: pass_tile<0, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        case 1: pass_tile<1, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        case 2: pass_tile<2, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        case 3: pass_tile<3, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
+        default: pass_tile<4, W, kMode, kSrc, kStrided, kJobs>(a, sm, tc); break;
         }
     }
 }
@@ -869,14 +880,14 @@ __host__ __device__ inline bool pass_kind_fits(const PassArgs& a, int kind)
     return kind != kKindInverse || (a.s > 0 && a.logC >= 2);
 }
 
-template <int W, int kKind>
+template <int W, int kKind, int kJobs>
 __device__ __forceinline__ void pass_tile_kind(const PassArgs& a, uint32_t* sm, uint32_t prime,
                                                const TileCoord& tc)
 {
     constexpr int kMode = kKind == kKindInverse ? kInverse
                         : (kKind == kKindFused || kKind == kKindFusedFirst) ? kFused : kForward;
     constexpr bool kSrc = kKind == kKindFirst || kKind == kKindFusedFirst;
-    pass_tile_any<W, kMode, kSrc, kKind == kKindInverse>(a, sm, prime, tc);
+    pass_tile_any<W, kMode, kSrc, kKind == kKindInverse, kJobs>(a, sm, prime, tc);
 }
 
 }  // namespace

@@ -114,11 +114,11 @@ __device__ __attribute__((noinline)) void run_item(ConstLaunch* Lp, uint32_t x, 
         const PassArgs pa = L->pass;
         const TileCoord tc{x, L->gx, z, false};
         switch (pass_kind(pa)) {
-        case kKindFirst: pass_tile_kind<W, kKindFirst>(pa, sm, y, tc); break;
-        case kKindForward: pass_tile_kind<W, kKindForward>(pa, sm, y, tc); break;
-        case kKindFusedFirst: pass_tile_kind<W, kKindFusedFirst>(pa, sm, y, tc); break;
-        case kKindFused: pass_tile_kind<W, kKindFused>(pa, sm, y, tc); break;
-        default: pass_tile_kind<W, kKindInverse>(pa, sm, y, tc); break;
+        case kKindFirst: pass_tile_kind<W, kKindFirst, 1>(pa, sm, y, tc); break;
+        case kKindForward: pass_tile_kind<W, kKindForward, 1>(pa, sm, y, tc); break;
+        case kKindFusedFirst: pass_tile_kind<W, kKindFusedFirst, 1>(pa, sm, y, tc); break;
+        case kKindFused: pass_tile_kind<W, kKindFused, 1>(pa, sm, y, tc); break;
+        default: pass_tile_kind<W, kKindInverse, 1>(pa, sm, y, tc); break;
         }
     } else {
         const CarryArgs ca = L->carry;

@@ -76,7 +76,7 @@ def test_no_scratch_no_vgpr_spill(src, tmp_path):
         return
     kernels = kernels_of(asm_path.read_text())
     passes = [k for k in kernels if "k_pass" in k]
-    assert len(passes) == 10            # two layouts x five kinds of pass
+    assert len(passes) == 18            # two layouts x (four kinds x single/batch + one-pass fused)
     for k in passes:
         lines = kernels[k]
         loops = innermost_loops(lines)
